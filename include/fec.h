@@ -1,0 +1,130 @@
+/*
+ * fec.h -- C ABI of the MI355X (gfx950) fixed-radius Euclidean clustering
+ * library (the clustering of "FEC: Fast Euclidean Clustering for Point Cloud
+ * Segmentation", arXiv 2208.07678).
+ *
+ * What is computed (Sec. 2.2, Eq. (1) and Alg. 1 of the paper):
+ *   Two points p_i, p_j are joined when they are closer than d.  The test is
+ *   Eq. (1)'s strict inequality evaluated in IEEE binary32, round to nearest,
+ *   with no contraction and no flush-to-zero, in the fixed order
+ *       dx = x_i - x_j, dy = y_i - y_j, dz = z_i - z_j,
+ *       s  = (dx*dx + dy*dy) + dz*dz,        joined  <=>  s < d*d
+ *   (d*d rounded to binary32).  Clusters are the connected components of
+ *   the graph of joined pairs, which is the set of segments Alg. 1's
+ *   point-wise loop arrives at when every point is visited and the neighbour
+ *   cap Th_max is unlimited.  A point with a non-finite coordinate is joined
+ *   to nothing.
+ *
+ * Output convention (fixed by this library; the paper labels segments in
+ * discovery order 1, 2, ...):
+ *   labels_out[i] = the smallest index j in i's cluster, when the cluster
+ *                   size |C| satisfies min_size <= |C| <= max_size
+ *                   (inclusive; min_size <= 0 acts as 1),
+ *                 = -1 otherwise.
+ *   The return value / *k_out is the number of clusters kept.
+ *   Labels are deterministic: they do not depend on scheduling.
+ *
+ * Memory: every buffer argument is a DEVICE pointer on the current HIP
+ * device, owned by the caller; the library never frees caller memory.
+ *   xyz        float32, array-of-structures [n][3] (x, y, z), contiguous,
+ *              4-byte aligned.  Read only.
+ *   labels_out int32 [n].  Written.
+ *
+ * Status codes (negative values are errors; no kernel is launched and no
+ * output is written when the host-side checks fail):
+ */
+#ifndef FEC_H
+#define FEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FEC_OK 0
+#define FEC_EINVAL (-1)  /* bad argument (checked on the host, before any launch)   */
+#define FEC_ERANGE (-2)  /* the point cloud's extent needs a grid key of more than  */
+                         /* 64 bits together with the point index (found on the    */
+                         /* device; labels_out is then filled with -1)              */
+#define FEC_ENOMEM (-3)  /* workspace allocation failed (blocking form only)        */
+#define FEC_EDEVICE (-4) /* a HIP runtime call failed, or a device-side consistency */
+                         /* check failed; see fec_last_error()                       */
+
+/*
+ * Blocking form.  Clusters n points with threshold d (Eq. (1)), applies the
+ * inclusive [min_size, max_size] size filter and writes labels_out.
+ * Runs on the stream set by fec_set_stream (default: the null stream) with a
+ * workspace the library allocates on first use and keeps (grown when a
+ * larger n arrives) until fec_release().  Waits for completion.
+ * Returns the number of kept clusters (>= 0) or a negative FEC_* status.
+ * Host-side checks (FEC_EINVAL): n < 0 or n > 2^31 - 1; d not finite, d <= 0,
+ * or d*d not a normal binary32 number; min_size > max_size; xyz or
+ * labels_out null while n > 0.  n == 0 returns 0 and touches nothing.
+ * Not safe to call concurrently from several host threads.
+ */
+int32_t fec_cluster(const float *xyz, int64_t n, float d, int32_t min_size, int32_t max_size,
+                    int32_t *labels_out);
+
+/*
+ * Workspace bytes fec_cluster_async needs for n points (0 for n <= 0).
+ * Linear in n (about 100-140 bytes per point).
+ */
+size_t fec_workspace_bytes(int64_t n);
+
+/*
+ * Asynchronous form: same computation, enqueued on `stream` (a hipStream_t,
+ * NULL for the null stream) with a caller-provided device workspace of at
+ * least fec_workspace_bytes(n) bytes (256-byte aligned).  Returns FEC_OK once
+ * the work is enqueued, or a negative status (host-side checks as for
+ * fec_cluster, plus FEC_EINVAL for a null or too small workspace; FEC_EDEVICE
+ * when a launch fails).  When the work completes, *k_out (a DEVICE int32, may
+ * be NULL) holds the number of kept clusters or FEC_ERANGE / FEC_EDEVICE.
+ * The workspace and outputs must not be used by other work until then; calls
+ * on distinct workspaces may run concurrently on distinct streams.
+ */
+int32_t fec_cluster_async(const float *xyz, int64_t n, float d, int32_t min_size,
+                          int32_t max_size, int32_t *labels_out, int32_t *k_out, void *workspace,
+                          size_t workspace_bytes, void *stream);
+
+/* Stream used by fec_cluster (a hipStream_t; NULL = null stream).  Returns FEC_OK. */
+int32_t fec_set_stream(void *stream);
+
+/* Frees the workspace cached by fec_cluster. */
+void fec_release(void);
+
+/* Message for the last non-OK status returned on this host thread ("" if none). */
+const char *fec_last_error(void);
+
+/* Library version string. */
+const char *fec_version(void);
+
+/*
+ * Diagnostics of the last call that used `workspace` (waits for `stream`):
+ * out[0] n, out[1] finite points, out[2] occupied grid cells, out[3] occupied
+ * grid columns, out[4] grid key bits, out[5] radix passes, out[6..8] grid
+ * cells along x, y, z, out[9] largest points per cell, out[10] status.
+ * Writes min(max_out, 11) values; returns that count or a negative status.
+ */
+int32_t fec_workspace_stats(const void *workspace, void *stream, int64_t *out, int32_t max_out);
+
+/*
+ * Kernel timing with HIP events recorded on the launch stream around the
+ * kernels of the stages selected by `stage_mask` (bit i = stage i; 0 turns
+ * timing off).  fec_profile_read waits for the recorded events, adds their
+ * durations to per-stage totals and writes, for i < max_stages, the total
+ * milliseconds and the number of timed launches of stage i; it returns the
+ * number of stages.  fec_profile_reset clears the totals.
+ */
+int32_t fec_profile_enable(uint64_t stage_mask);
+int32_t fec_profile_read(double *ms_total, int64_t *launches, int32_t max_stages);
+void fec_profile_reset(void);
+int32_t fec_stage_count(void);
+const char *fec_stage_name(int32_t stage);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEC_H */

@@ -1,0 +1,221 @@
+"""MI355X (gfx950) fixed-radius Euclidean clustering -- Python binding.
+
+Thin ctypes layer over the C ABI declared in include/fec.h and implemented by
+the in-tree HIP library ``libfec_hip.so`` (built by
+``python -m paper_2208_07678_amd.build``).  PyTorch only provides device
+memory and the current stream; every step of the clustering runs in the HIP
+kernels.  There is no CPU fallback: every entry point raises when the built
+library is missing, and tensors must live on the GPU.
+
+    labels, k = paper_2208_07678_amd.cluster(xyz, d, min_size, max_size)
+
+``xyz`` is a contiguous float32 CUDA tensor [n, 3]; ``labels`` is an int32
+CUDA tensor [n] with the smallest point index of each kept cluster, -1 for
+points of clusters whose size is outside [min_size, max_size].
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "cluster", "cluster_async", "workspace_bytes", "workspace_stats", "FecError",
+    "profile_enable", "profile_read", "profile_reset", "stage_names", "lib_path",
+    "FEC_OK", "FEC_EINVAL", "FEC_ERANGE", "FEC_ENOMEM", "FEC_EDEVICE",
+]
+
+FEC_OK = 0
+FEC_EINVAL = -1
+FEC_ERANGE = -2
+FEC_ENOMEM = -3
+FEC_EDEVICE = -4
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "libfec_hip.so")
+
+_lib = None
+
+
+def _load():
+    """Loads the HIP library; raises when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(lib_path):
+        raise ImportError(
+            "paper_2208_07678_amd: HIP library %s is missing; build it with "
+            "'python -m paper_2208_07678_amd.build'" % lib_path)
+    lib = ctypes.CDLL(lib_path)
+    i32, i64, f32, vp, u64 = (ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_void_p,
+                              ctypes.c_uint64)
+    sigs = {
+        "fec_cluster": ([vp, i64, f32, i32, i32, vp], i32),
+        "fec_workspace_bytes": ([i64], ctypes.c_size_t),
+        "fec_cluster_async": ([vp, i64, f32, i32, i32, vp, vp, vp, ctypes.c_size_t, vp], i32),
+        "fec_set_stream": ([vp], i32),
+        "fec_release": ([], None),
+        "fec_last_error": ([], ctypes.c_char_p),
+        "fec_version": ([], ctypes.c_char_p),
+        "fec_workspace_stats": ([vp, vp, vp, i32], i32),
+        "fec_profile_enable": ([u64], i32),
+        "fec_profile_read": ([vp, vp, i32], i32),
+        "fec_profile_reset": ([], None),
+        "fec_stage_count": ([], i32),
+        "fec_stage_name": ([i32], ctypes.c_char_p),
+    }
+    for name, (args, res) in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+EXPORTED = [
+    "fec_cluster", "fec_workspace_bytes", "fec_cluster_async", "fec_set_stream", "fec_release",
+    "fec_last_error", "fec_version", "fec_workspace_stats", "fec_profile_enable",
+    "fec_profile_read", "fec_profile_reset", "fec_stage_count", "fec_stage_name",
+]
+
+STATS_FIELDS = ["n", "finite_points", "cells", "columns", "key_bits", "radix_passes",
+                "grid_x", "grid_y", "grid_z", "max_points_per_cell", "status"]
+
+
+class FecError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("FEC error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _raise(code: int):
+    raise FecError(code, (_load().fec_last_error() or b"").decode())
+
+
+def version() -> str:
+    return _load().fec_version().decode()
+
+
+def workspace_bytes(n: int) -> int:
+    return int(_load().fec_workspace_bytes(int(n)))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check_xyz(xyz):
+    torch = _torch()
+    if not isinstance(xyz, torch.Tensor):
+        raise TypeError("xyz must be a torch tensor on a GPU")
+    if xyz.device.type != "cuda":
+        raise ValueError("xyz must be on a GPU (got %s); there is no CPU path" % xyz.device)
+    if xyz.dtype != torch.float32 or xyz.dim() != 2 or xyz.shape[1] != 3:
+        raise ValueError("xyz must be float32 [n, 3]")
+    if not xyz.is_contiguous():
+        raise ValueError("xyz must be contiguous")
+
+
+def new_workspace(n: int, device):
+    """A device workspace (uint8 tensor) large enough for n points."""
+    torch = _torch()
+    nb = max(workspace_bytes(n), 256)
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device=device)
+    return ws
+
+
+def _aligned_ptr(ws) -> tuple[int, int]:
+    p = ws.data_ptr()
+    a = (p + 255) // 256 * 256
+    return a, ws.numel() - (a - p)
+
+
+def cluster_async(xyz, d: float, min_size: int = 1, max_size: int = 2**31 - 1, *,
+                  labels=None, k_out=None, workspace=None, stream=None):
+    """Enqueues the clustering on the current (or given) stream.
+
+    Returns (labels, k_out, workspace): labels int32 [n] and k_out int32 [1]
+    are device tensors written when the stream reaches the work.
+    """
+    torch = _torch()
+    _check_xyz(xyz)
+    n = xyz.shape[0]
+    dev = xyz.device
+    if labels is None:
+        labels = torch.empty(n, dtype=torch.int32, device=dev)
+    if k_out is None:
+        k_out = torch.empty(1, dtype=torch.int32, device=dev)
+    if workspace is None:
+        workspace = new_workspace(n, dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    wptr, wbytes = _aligned_ptr(workspace)
+    with torch.cuda.device(dev):
+        rc = _load().fec_cluster_async(ctypes.c_void_p(xyz.data_ptr()), n, float(d), int(min_size),
+                                    int(max_size), ctypes.c_void_p(labels.data_ptr()),
+                                    ctypes.c_void_p(k_out.data_ptr()), ctypes.c_void_p(wptr),
+                                    wbytes, ctypes.c_void_p(stream.cuda_stream))
+    if rc != FEC_OK:
+        _raise(rc)
+    return labels, k_out, workspace
+
+
+def cluster(xyz, d: float, min_size: int = 1, max_size: int = 2**31 - 1, *,
+            workspace=None, labels=None, stream=None):
+    """Clusters xyz; returns (labels int32 CUDA tensor [n], kept cluster count)."""
+    labels, k_out, _ = cluster_async(xyz, d, min_size, max_size, labels=labels,
+                                     workspace=workspace, stream=stream)
+    k = int(k_out.item())
+    if k < 0:
+        raise FecError(k, "device-side status %d" % k)
+    return labels, k
+
+
+def workspace_stats(workspace, stream=None) -> dict:
+    """Diagnostics of the last call that used ``workspace``."""
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream(workspace.device)
+    out = (ctypes.c_int64 * len(STATS_FIELDS))()
+    wptr, _ = _aligned_ptr(workspace)
+    rc = _load().fec_workspace_stats(ctypes.c_void_p(wptr), ctypes.c_void_p(stream.cuda_stream),
+                                  out, len(STATS_FIELDS))
+    if rc < 0:
+        _raise(rc)
+    return {k: int(out[i]) for i, k in enumerate(STATS_FIELDS[:rc])}
+
+
+def stage_names() -> list[str]:
+    return [_load().fec_stage_name(i).decode() for i in range(_load().fec_stage_count())]
+
+
+def profile_enable(stages=None) -> None:
+    """Time the named stages (all when None) with HIP events; [] turns timing off."""
+    names = stage_names()
+    if stages is None:
+        mask = (1 << len(names)) - 1
+    else:
+        mask = 0
+        for s in stages:
+            mask |= 1 << names.index(s)
+    _load().fec_profile_enable(mask)
+
+
+def profile_read() -> dict:
+    """{stage: (total ms, timed launches)} accumulated since the last reset."""
+    ns = _load().fec_stage_count()
+    ms = (ctypes.c_double * ns)()
+    cnt = (ctypes.c_int64 * ns)()
+    _load().fec_profile_read(ms, cnt, ns)
+    names = stage_names()
+    return {names[i]: (float(ms[i]), int(cnt[i])) for i in range(ns)}
+
+
+def profile_reset() -> None:
+    _load().fec_profile_reset()
+
+
+def raw_lib():
+    """The loaded ctypes library (for ABI tests)."""
+    return _load()

@@ -1,0 +1,253 @@
+// C ABI of the clustering library: argument checks, workspace handling,
+// stream selection, diagnostics and kernel timing.  The computation itself
+// is enqueued by fec::launch_pipeline (fec_device.hip).
+
+#include "../../include/fec.h"
+#include "fec_internal.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int32_t fail(int32_t code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int32_t ok() {
+    g_err.clear();
+    return FEC_OK;
+}
+
+// Host-side argument checks shared by both forms.
+int32_t check_args(const float *xyz, int64_t n, float d, int32_t min_size, int32_t max_size,
+                   const int32_t *labels_out) {
+    if (n < 0 || n > 2147483647LL)
+        return fail(FEC_EINVAL, "n=%lld outside [0, 2^31-1]", (long long)n);
+    if (!std::isfinite(d) || !(d > 0.0f))
+        return fail(FEC_EINVAL, "d=%g must be finite and > 0", (double)d);
+    const float d2 = d * d;
+    if (!std::isnormal(d2))
+        return fail(FEC_EINVAL, "d*d=%g is not a normal binary32 number", (double)d2);
+    if (min_size > max_size)
+        return fail(FEC_EINVAL, "min_size=%d > max_size=%d", min_size, max_size);
+    if (n > 0 && (xyz == nullptr || labels_out == nullptr))
+        return fail(FEC_EINVAL, "null xyz or labels_out with n=%lld", (long long)n);
+    return FEC_OK;
+}
+
+// ----------------------------------------------------------------- timing
+struct EventTimer final : fec::Timer {
+    uint64_t mask = 0;
+    struct Rec {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    double total_ms[fec::kNumStages] = {};
+    int64_t count[fec::kNumStages] = {};
+    hipEvent_t open_ev = nullptr;
+
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void begin(int stage, hipStream_t s) override {
+        if (!((mask >> stage) & 1)) return;
+        open_ev = get();
+        if (open_ev) (void)hipEventRecord(open_ev, s);
+    }
+    void end(int stage, hipStream_t s) override {
+        if (!((mask >> stage) & 1) || !open_ev) return;
+        hipEvent_t b = get();
+        if (!b) return;
+        (void)hipEventRecord(b, s);
+        pending.push_back({stage, open_ev, b});
+        open_ev = nullptr;
+    }
+    int collect() {
+        for (auto &r : pending) {
+            float ms = 0.f;
+            if (hipEventSynchronize(r.b) == hipSuccess &&
+                hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                total_ms[r.stage] += ms;
+                count[r.stage] += 1;
+            }
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        pending.clear();
+        return fec::kNumStages;
+    }
+};
+
+std::mutex g_mu;
+EventTimer g_timer;
+
+// ----------------------------------------------------------------- blocking form state
+struct Cached {
+    void *ws = nullptr;
+    size_t bytes = 0;
+    int32_t *k_dev = nullptr;
+    hipStream_t stream = nullptr;
+} g_cache;
+
+}  // namespace
+
+extern "C" {
+
+const char *fec_version(void) { return "fec-mi355x 0.1 (gfx950)"; }
+
+const char *fec_last_error(void) { return g_err.c_str(); }
+
+size_t fec_workspace_bytes(int64_t n) {
+    if (n <= 0) return 0;
+    return fec::make_layout(n).total;
+}
+
+int32_t fec_cluster_async(const float *xyz, int64_t n, float d, int32_t min_size,
+                          int32_t max_size, int32_t *labels_out, int32_t *k_out, void *workspace,
+                          size_t workspace_bytes, void *stream) {
+    int32_t rc = check_args(xyz, n, d, min_size, max_size, labels_out);
+    if (rc != FEC_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (n == 0) {
+        if (k_out) {
+            int32_t zero = 0;
+            if (hipMemcpyAsync(k_out, &zero, sizeof zero, hipMemcpyHostToDevice, st) !=
+                hipSuccess)
+                return fail(FEC_EDEVICE, "hipMemcpyAsync of k failed");
+            if (hipStreamSynchronize(st) != hipSuccess)
+                return fail(FEC_EDEVICE, "hipStreamSynchronize failed");
+        }
+        return ok();
+    }
+    const fec::Layout L = fec::make_layout(n);
+    if (workspace == nullptr || workspace_bytes < L.total)
+        return fail(FEC_EINVAL, "workspace of %zu bytes is smaller than the %zu needed",
+                    workspace_bytes, L.total);
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0)
+        return fail(FEC_EINVAL, "workspace is not 256-byte aligned");
+    hipError_t e;
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        e = fec::launch_pipeline(xyz, n, d, min_size, max_size, labels_out, k_out, workspace, L,
+                                 st, g_timer.mask ? &g_timer : nullptr);
+    }
+    if (e != hipSuccess) return fail(FEC_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+int32_t fec_set_stream(void *stream) {
+    g_cache.stream = static_cast<hipStream_t>(stream);
+    return ok();
+}
+
+void fec_release(void) {
+    if (g_cache.ws) (void)hipFree(g_cache.ws);
+    if (g_cache.k_dev) (void)hipFree(g_cache.k_dev);
+    g_cache.ws = nullptr;
+    g_cache.k_dev = nullptr;
+    g_cache.bytes = 0;
+}
+
+int32_t fec_cluster(const float *xyz, int64_t n, float d, int32_t min_size, int32_t max_size,
+                    int32_t *labels_out) {
+    int32_t rc = check_args(xyz, n, d, min_size, max_size, labels_out);
+    if (rc != FEC_OK) return rc;
+    if (n == 0) return ok();
+    const size_t need = fec_workspace_bytes(n);
+    if (g_cache.bytes < need) {
+        if (g_cache.ws) (void)hipFree(g_cache.ws);
+        g_cache.ws = nullptr;
+        g_cache.bytes = 0;
+        if (hipMalloc(&g_cache.ws, need) != hipSuccess) {
+            g_cache.ws = nullptr;
+            return fail(FEC_ENOMEM, "hipMalloc of %zu workspace bytes failed", need);
+        }
+        g_cache.bytes = need;
+    }
+    if (!g_cache.k_dev && hipMalloc(&g_cache.k_dev, sizeof(int32_t)) != hipSuccess) {
+        g_cache.k_dev = nullptr;
+        return fail(FEC_ENOMEM, "hipMalloc of the result word failed");
+    }
+    rc = fec_cluster_async(xyz, n, d, min_size, max_size, labels_out, g_cache.k_dev, g_cache.ws,
+                           g_cache.bytes, g_cache.stream);
+    if (rc != FEC_OK) return rc;
+    int32_t k = 0;
+    if (hipMemcpyAsync(&k, g_cache.k_dev, sizeof k, hipMemcpyDeviceToHost, g_cache.stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(g_cache.stream) != hipSuccess)
+        return fail(FEC_EDEVICE, "reading the result failed: %s",
+                    hipGetErrorString(hipGetLastError()));
+    if (k == FEC_ERANGE) return fail(FEC_ERANGE, "grid key of the cloud's extent exceeds 64 bits");
+    if (k < 0) return fail(k, "device-side failure (status %d)", k);
+    return k;
+}
+
+int32_t fec_workspace_stats(const void *workspace, void *stream, int64_t *out, int32_t max_out) {
+    if (!workspace || !out || max_out <= 0) return fail(FEC_EINVAL, "bad arguments");
+    fec::Params P;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(&P, workspace, sizeof P, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(FEC_EDEVICE, "reading the workspace failed");
+    const int64_t v[11] = {P.n,  P.nvalid, P.M,  P.Mcol, P.key_bits, P.npasses,
+                           P.NX, P.NY,     P.NZ, P.max_cell, P.status};
+    const int32_t c = max_out < 11 ? max_out : 11;
+    for (int32_t i = 0; i < c; ++i) out[i] = v[i];
+    ok();
+    return c;
+}
+
+int32_t fec_profile_enable(uint64_t stage_mask) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_timer.mask = stage_mask;
+    return ok();
+}
+
+int32_t fec_profile_read(double *ms_total, int64_t *launches, int32_t max_stages) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    const int ns = g_timer.collect();
+    for (int i = 0; i < ns && i < max_stages; ++i) {
+        if (ms_total) ms_total[i] = g_timer.total_ms[i];
+        if (launches) launches[i] = g_timer.count[i];
+    }
+    return ns;
+}
+
+void fec_profile_reset(void) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_timer.collect();
+    for (int i = 0; i < fec::kNumStages; ++i) {
+        g_timer.total_ms[i] = 0.0;
+        g_timer.count[i] = 0;
+    }
+}
+
+int32_t fec_stage_count(void) { return fec::kNumStages; }
+
+const char *fec_stage_name(int32_t stage) { return fec::stage_name(stage); }
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// Internal definitions shared by the device pipeline and the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fec {
+
+// ---------------------------------------------------------------- tiling
+constexpr int kBlock = 256;            // threads per block of the streaming kernels
+constexpr int kItems = 16;             // elements per thread in tiled kernels
+constexpr int kTile = kBlock * kItems; // elements per tile (sort, gather, cells)
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kMaxPasses = (64 + kRadixBits - 1) / kRadixBits;
+constexpr int kBboxBlocks = 1024;      // max blocks of the bounding-box reduction
+constexpr int kCellBlocks = 4096;      // grid of the grid-stride per-cell kernels
+
+// Look-back words of the radix passes: 2-bit flag + 62-bit count.
+constexpr uint64_t kLbAggregate = 1ull << 62;
+constexpr uint64_t kLbInclusive = 2ull << 62;
+constexpr uint64_t kLbValue = (1ull << 62) - 1;
+
+constexpr uint64_t kHashEmpty = ~0ull;
+
+// Device-side status values (mirror the public FEC_* codes).
+constexpr int32_t kStatusOk = 0;
+constexpr int32_t kStatusRange = -2;
+constexpr int32_t kStatusDevice = -4;
+
+// Per-call state, kept at the start of the workspace.  Written by the
+// planning kernel, read by every later kernel of the call.
+struct Params {
+    int64_t n;
+    float d;
+    float d2;          // fl32(d * d): the predicate's threshold
+    int32_t min_size;  // already clamped to >= 1
+    int32_t max_size;
+    int32_t status;
+    int32_t pad0;
+    int64_t nvalid;    // points with three finite coordinates
+    double ox, oy, oz; // grid origin: the bounding box minimum of finite points
+    double inv_s;      // 1 / cell side
+    int64_t NX, NY, NZ;
+    int32_t bx, by, bz;   // key bits per axis: key = cx << (by+bz) | cy << bz | cz
+    int32_t key_bits;     // bits sorted (grid key, plus one for non-finite points)
+    int32_t idx_bits;     // bits of the point index packed below the key
+    int32_t npasses;      // radix passes actually run
+    uint64_t idx_mask;
+    int64_t M;            // occupied cells
+    int64_t Mcol;         // occupied columns (cells sharing cx, cy)
+    uint64_t hmask;       // column hash capacity - 1
+    int32_t kept;         // kept clusters
+    int32_t max_cell;     // largest number of points in one cell
+    uint32_t ticket[kMaxPasses];
+    uint32_t hist[kMaxPasses][kRadix];
+};
+
+// ---------------------------------------------------------------- workspace
+struct Layout {
+    size_t params, partials, tile_cnt, tile_off;
+    size_t keys0, keys1, lb0, lb1;
+    size_t spts, sorig, cell_start, cell_key, cpar, csize, ccanon;
+    size_t hkeys, hvals;
+    size_t total;
+    int64_t ntiles;
+    uint64_t hcap_max;
+};
+
+inline uint64_t next_pow2(uint64_t v) {
+    uint64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+inline Layout make_layout(int64_t n) {
+    Layout L{};
+    const size_t A = 256;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, A);
+        return o;
+    };
+    const size_t un = (size_t)(n > 0 ? n : 1);
+    L.ntiles = (int64_t)((un + kTile - 1) / kTile);
+    L.hcap_max = next_pow2(2 * un < 64 ? 64 : 2 * un);
+    L.params = take(sizeof(Params));
+    L.partials = take((size_t)kBboxBlocks * 8 * sizeof(float));
+    L.tile_cnt = take((size_t)L.ntiles * 2 * sizeof(uint32_t));
+    L.tile_off = take((size_t)L.ntiles * 2 * sizeof(uint32_t));
+    L.keys0 = take(un * sizeof(uint64_t));
+    L.keys1 = take(un * sizeof(uint64_t));
+    L.lb0 = take((size_t)L.ntiles * kRadix * sizeof(uint64_t));
+    L.lb1 = take((size_t)L.ntiles * kRadix * sizeof(uint64_t));
+    L.spts = take(un * sizeof(float4));
+    L.sorig = take(un * sizeof(uint32_t));
+    L.cell_start = take((un + 1) * sizeof(uint32_t));
+    L.cell_key = take(un * sizeof(uint64_t));
+    L.cpar = take(un * sizeof(int32_t));
+    L.csize = take(un * sizeof(int32_t));
+    L.ccanon = take(un * sizeof(int32_t));
+    L.hkeys = take((size_t)L.hcap_max * sizeof(uint64_t));
+    L.hvals = take((size_t)L.hcap_max * sizeof(uint64_t));
+    L.total = off;
+    return L;
+}
+
+// ---------------------------------------------------------------- stages
+enum Stage : int {
+    kStBbox = 0,
+    kStPlan,
+    kStKeys,
+    kStSort,
+    kStGather,
+    kStTileScan,
+    kStHashClear,
+    kStCells,
+    kStColumns,
+    kStHookNear,
+    kStCompress1,
+    kStHookFar,
+    kStCompress2,
+    kStFinalCells,
+    kStFinalLabels,
+    kStFinish,
+    kNumStages
+};
+
+const char *stage_name(int s);
+
+// Timing hook: called around each launch; records events when enabled.
+struct Timer {
+    virtual void begin(int stage, hipStream_t s) = 0;
+    virtual void end(int stage, hipStream_t s) = 0;
+    virtual ~Timer() {}
+};
+
+// Enqueues the whole pipeline.  Returns hipSuccess or the first launch error.
+hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_size,
+                           int32_t max_size, int32_t *labels_out, int32_t *k_out, void *ws,
+                           const Layout &L, hipStream_t stream, Timer *timer);
+
+}  // namespace fec

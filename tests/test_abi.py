@@ -1,0 +1,83 @@
+"""The C ABI library loads on the CPU host and exports what include/fec.h declares.
+
+No compute call is made here (no GPU); only host-side entry points that do
+not touch a device: argument checks, workspace sizing, names.
+"""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fec.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fec_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def fec():
+    import paper_2208_07678_amd as fec
+    if not os.path.exists(fec.lib_path):
+        pytest.fail("HIP library not built: run python -m paper_2208_07678_amd.build")
+    fec._load()
+    return fec
+
+
+def test_every_declared_symbol_is_exported(fec):
+    names = _declared()
+    assert len(names) >= 10
+    lib = fec.raw_lib()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(fec.EXPORTED) == names
+
+
+def test_workspace_bytes_linear(fec):
+    assert fec.workspace_bytes(0) == 0
+    assert fec.workspace_bytes(-5) == 0
+    a, b = fec.workspace_bytes(1_000_000), fec.workspace_bytes(2_000_000)
+    assert 60 * 1_000_000 < a < 200 * 1_000_000
+    assert b > a
+
+
+def test_stage_names(fec):
+    names = fec.stage_names()
+    assert "hook_near" in names and "sort_pass" in names and len(names) == len(set(names))
+
+
+def test_host_side_argument_checks(fec):
+    lib = fec.raw_lib()
+    buf = ctypes.c_void_p(0x1000)   # never dereferenced: checks fail first
+    ws = ctypes.c_void_p(0x100000)
+    cases = [
+        (-1, 0.5, 1, 5), (2**31, 0.5, 1, 5), (10, 0.0, 1, 5), (10, -1.0, 1, 5),
+        (10, float("nan"), 1, 5), (10, float("inf"), 1, 5), (10, 1e-30, 1, 5), (10, 0.5, 6, 5),
+    ]
+    for n, d, mn, mx in cases:
+        rc = lib.fec_cluster_async(buf, n, ctypes.c_float(d), mn, mx, buf, None, ws, 1 << 40, None)
+        assert rc == fec.FEC_EINVAL, (n, d, mn, mx)
+        assert lib.fec_last_error()
+    # null pointers with n > 0
+    rc = lib.fec_cluster_async(None, 10, ctypes.c_float(0.5), 1, 5, buf, None, ws, 1 << 40, None)
+    assert rc == fec.FEC_EINVAL
+    # workspace too small / misaligned
+    rc = lib.fec_cluster_async(buf, 10, ctypes.c_float(0.5), 1, 5, buf, None, ws, 16, None)
+    assert rc == fec.FEC_EINVAL
+    rc = lib.fec_cluster_async(buf, 10, ctypes.c_float(0.5), 1, 5, buf, None,
+                               ctypes.c_void_p(0x100001), 1 << 40, None)
+    assert rc == fec.FEC_EINVAL
+    # n == 0 with no k_out: nothing to do, no device touched
+    rc = lib.fec_cluster_async(None, 0, ctypes.c_float(0.5), 1, 5, None, None, None, 0, None)
+    assert rc == fec.FEC_OK
+
+
+def test_cpu_tensors_are_refused(fec):
+    import torch
+    with pytest.raises(ValueError):
+        fec.cluster(torch.zeros((4, 3)), 0.5)

@@ -1,0 +1,87 @@
+"""Error behaviour of the C ABI on the GPU (status codes, no output on error)."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import gpu_cluster, say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_blocking_form_matches_async():
+    import torch
+
+    import oracle
+    import paper_2208_07678_amd as fec
+    lib = fec.raw_lib()
+    xyz = synth.blobs_cloud(seed=4)
+    t = torch.from_numpy(xyz).cuda()
+    out = torch.full((xyz.shape[0],), 123, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    lib.fec_set_stream(None)
+    k = lib.fec_cluster(ctypes.c_void_p(t.data_ptr()), xyz.shape[0], ctypes.c_float(0.5), 10,
+                        20000, ctypes.c_void_p(out.data_ptr()))
+    want, wk = oracle.fec(xyz, 0.5, 10, 20000)
+    assert k == wk
+    assert np.array_equal(out.cpu().numpy(), want)
+    lib.fec_release()
+
+
+def test_invalid_arguments_leave_output_untouched():
+    import torch
+
+    import paper_2208_07678_amd as fec
+    x = torch.zeros((10, 3), dtype=torch.float32, device="cuda")
+    out = torch.full((10,), 77, dtype=torch.int32, device="cuda")
+    for d, mn, mx in ((0.0, 1, 5), (float("nan"), 1, 5), (1e-30, 1, 5), (0.5, 6, 5),
+                      (float("inf"), 1, 5), (-1.0, 1, 5)):
+        say("invalid", d, mn, mx)
+        with pytest.raises(fec.FecError) as ei:
+            fec.cluster(x, d, mn, mx, labels=out)
+        assert ei.value.code == fec.FEC_EINVAL
+    torch.cuda.synchronize()
+    assert (out.cpu().numpy() == 77).all()
+
+
+def test_range_error_for_huge_extent():
+    import torch
+
+    import paper_2208_07678_amd as fec
+    x = np.array([[0, 0, 0], [3e37, 0, 0], [0, 3e37, 0], [0, 0, 3e37]], dtype=np.float32)
+    t = torch.from_numpy(x).cuda()
+    labels, k_out, _ = fec.cluster_async(t, 1.0, 1, 10)
+    torch.cuda.synchronize()
+    assert int(k_out.item()) == fec.FEC_ERANGE
+    assert (labels.cpu().numpy() == -1).all()
+
+
+def test_empty_and_single():
+    got, k = gpu_cluster(np.zeros((0, 3), np.float32), 0.5, 1, 10)
+    assert got.shape == (0,) and k == 0
+    got, k = gpu_cluster(np.array([[1, 2, 3]], np.float32), 0.5, 1, 10)
+    assert got.tolist() == [0] and k == 1
+    got, k = gpu_cluster(np.array([[1, 2, 3]], np.float32), 0.5, 2, 10)
+    assert got.tolist() == [-1] and k == 0
+
+
+def test_workspace_stats_and_profile():
+    import torch
+
+    import paper_2208_07678_amd as fec
+    xyz, d, mn, mx = synth.make_config("lidar120k")
+    t = torch.from_numpy(xyz).cuda()
+    ws = fec.new_workspace(xyz.shape[0], "cuda")
+    fec.profile_reset()
+    fec.profile_enable()
+    fec.cluster(t, d, mn, mx, workspace=ws)
+    prof = fec.profile_read()
+    fec.profile_enable([])
+    st = fec.workspace_stats(ws)
+    say(st)
+    say(prof)
+    assert st["n"] == xyz.shape[0] and st["finite_points"] == xyz.shape[0]
+    assert 0 < st["cells"] <= xyz.shape[0] and st["status"] == 0
+    assert prof["hook_near"][1] == 1 and prof["hook_near"][0] > 0

@@ -1,0 +1,151 @@
+"""GPU parity: labels of the HIP path equal the CPU oracle's, bit for bit.
+
+Every case runs through the C ABI (fec_cluster_async via the ctypes
+binding) on cuda:0 and is compared element by element with oracle.fec on
+the same seeded input.  Integer labels: the bar is exact equality.
+"""
+
+import numpy as np
+import pytest
+
+import goldens
+import oracle
+import synth
+from gpu_helpers import describe_mismatch, gpu_cluster, say
+from oracle import invariants
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(xyz, d, mn, mx, tag):
+    say("case", tag, "n=%d d=%g min=%d max=%d" % (xyz.shape[0], d, mn, mx))
+    got, k = gpu_cluster(xyz, d, mn, mx)
+    want, wk = oracle.fec(xyz, d, mn, mx)
+    assert np.array_equal(got, want), "%s: %s" % (tag, describe_mismatch(got, want))
+    assert k == wk, "%s: k gpu %d oracle %d" % (tag, k, wk)
+    return got, k
+
+
+def test_golden_fixtures():
+    for name, xyz, d, mn, mx, k, labels in goldens.all_cases():
+        say("fixture", name)
+        got, gk = gpu_cluster(xyz, d, mn, mx)
+        assert np.array_equal(got, labels), (name, got, labels)
+        assert gk == k
+
+
+def _small(seed):
+    rng = np.random.default_rng(seed)
+    kind = seed % 6
+    n = int(rng.integers(1, 3000))
+    if kind == 0:
+        x = synth.random_cloud(n, extent=(6, 6, 2), seed=seed)
+        d = float(rng.uniform(0.1, 0.8))
+    elif kind == 1:
+        c = rng.uniform(0, 20, size=(int(rng.integers(1, 12)), 3))
+        x = (c[rng.integers(0, c.shape[0], n)] + rng.normal(0, 0.5, (n, 3))).astype(np.float32)
+        d = float(rng.uniform(0.1, 0.6))
+    elif kind == 2:
+        d = float(rng.choice([0.5, 0.35, 0.2, 1.0]))
+        x = synth.near_threshold_cloud(max(1, n // 2), d, seed=seed, spread=4.0)
+    elif kind == 3:
+        x = synth.random_cloud(n, extent=(30, 30, 0.0), seed=seed, offset=(-1800, 900, -3))
+        d = float(rng.uniform(0.2, 1.5))
+    elif kind == 4:
+        x = synth.random_cloud(n, extent=(2, 2, 2), seed=seed)
+        bad = rng.random(n) < 0.1
+        vals = np.array([np.nan, np.inf, -np.inf], dtype=np.float32)
+        x[bad, rng.integers(0, 3)] = vals[rng.integers(0, 3, int(bad.sum()))]
+        d = float(rng.uniform(0.05, 0.4))
+    else:
+        d = float(rng.uniform(0.1, 0.5))
+        x = synth.chain_cloud(n, d * float(rng.uniform(0.7, 1.3)), axis=int(rng.integers(0, 3)))
+        x = x[rng.permutation(n)]
+    mn = int(rng.integers(0, 5))
+    mx = int(rng.integers(max(1, mn), n + 3))
+    return x, d, mn, max(mn, mx)
+
+
+def test_many_small_clouds():
+    for seed in range(300):
+        x, d, mn, mx = _small(seed)
+        _check(x, d, mn, mx, "small seed %d" % seed)
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 4095, 4096, 4097, 8191, 12289])
+def test_ragged_sizes(n):
+    x = synth.random_cloud(n, extent=(8, 8, 8), seed=n)
+    _check(x, 0.45, 1, n, "ragged %d" % n)
+
+
+def test_blobs20k():
+    xyz, d, mn, mx = synth.make_config("blobs20k")
+    _check(xyz, d, mn, mx, "blobs20k")
+    _check(xyz, d, 1, xyz.shape[0], "blobs20k unfiltered")
+
+
+def test_lidar120k_and_shuffled():
+    xyz, d, mn, mx = synth.make_config("lidar120k")
+    _check(xyz, d, mn, mx, "lidar120k")
+    perm = np.random.default_rng(5).permutation(xyz.shape[0])
+    _check(xyz[perm], d, mn, mx, "lidar120k shuffled")
+
+
+def test_map_prefix_full_oracle():
+    xyz = synth.lidar_map(frames=list(range(6)))
+    _check(xyz, 0.2, 100, 5000000, "map 6 frames")
+
+
+def test_degenerate_inputs():
+    # all points identical: one cell, one cluster
+    x = np.full((5000, 3), 7.25, dtype=np.float32)
+    _check(x, 0.3, 1, 5000, "duplicates")
+    _check(x, 0.3, 1, 4999, "duplicates filtered")
+    # all non-finite
+    y = np.full((100, 3), np.nan, dtype=np.float32)
+    _check(y, 0.3, 1, 10, "all nan")
+    _check(y, 0.3, 2, 10, "all nan filtered")
+    # d below every distance / above the diagonal (Fig. 3 cases 2 and 1)
+    z = synth.random_cloud(3000, extent=(10, 10, 10), seed=2)
+    _check(z, 1e-4, 1, 3000, "tiny d")
+    _check(z, 30.0, 1, 3000, "huge d")
+    # points on a line (Fig. 3 case 3), both sides of the threshold
+    c = synth.chain_cloud(10000, 0.25, axis=2)
+    _check(c, 0.25, 1, 10000, "chain at d (strict)")
+    _check(c, float(np.nextafter(np.float32(0.25), np.float32(1))), 1, 10000, "chain above d")
+
+
+def test_repeatable_bitwise():
+    xyz, d, mn, mx = synth.make_config("lidar120k")
+    first, k = gpu_cluster(xyz, d, mn, mx)
+    for r in range(4):
+        say("repeat", r)
+        again, k2 = gpu_cluster(xyz, d, mn, mx)
+        assert np.array_equal(first, again) and k == k2
+
+
+def test_workspace_reuse_across_sizes():
+    import torch
+
+    import paper_2208_07678_amd as fec
+    big = synth.random_cloud(50000, extent=(20, 20, 5), seed=3)
+    ws = fec.new_workspace(50000, "cuda:0")
+    for n in (50000, 1000, 37, 50000, 20000):
+        x = big[:n]
+        say("reuse n", n)
+        got, k = gpu_cluster(x, 0.3, 1, n, workspace=ws)
+        want, wk = oracle.fec(x, 0.3, 1, n)
+        assert np.array_equal(got, want) and k == wk
+    torch.cuda.synchronize()
+
+
+def test_invariants_map_prefix():
+    xyz = synth.lidar_map(frames=[10, 11, 12])
+    got, k = gpu_cluster(xyz, 0.2, 1, xyz.shape[0])
+    assert invariants.partition_problems(got) == []
+    idx = oracle.Index(xyz, 0.2)
+    sample = np.random.default_rng(3).choice(xyz.shape[0], 5000, replace=False)
+    assert invariants.closure_problems(idx, got, sample) == []
+    filt, kf = gpu_cluster(xyz, 0.2, 100, 5000000)
+    assert invariants.filter_problems(filt, got, 100, 5000000) == []
+    assert invariants.count_kept(filt) == kf
