@@ -248,7 +248,11 @@ __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ parti
     P->key_bits = kb;
     P->idx_bits = ib;
     P->idx_mask = (1ull << ib) - 1;
-    if (kb + ib > 64) P->status = kStatusRange;
+    // One 64-bit word per point when key and index fit together, otherwise
+    // separate key and index arrays; beyond a 64-bit key the grid is refused.
+    P->pair_mode = (kb + ib > 64) ? 1 : 0;
+    P->key_shift = P->pair_mode ? 0 : ib;
+    if (kb > 64) P->status = kStatusRange;
     P->npasses = P->status == kStatusOk ? (kb + kRadixBits - 1) / kRadixBits : 0;
 }
 
@@ -258,6 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ parti
 __global__ __launch_bounds__(kBlock) void k_keys(const float *__restrict__ xyz,
                                                  Params *__restrict__ P,
                                                  uint64_t *__restrict__ keys,
+                                                 uint32_t *__restrict__ vals,
                                                  uint64_t *__restrict__ lb0, int64_t lb_words) {
     __shared__ uint32_t sh[kMaxPasses][kRadix];
     if (P->status != kStatusOk) return;
@@ -265,7 +270,8 @@ __global__ __launch_bounds__(kBlock) void k_keys(const float *__restrict__ xyz,
     __syncthreads();
     const int64_t n = P->n;
     const int np = P->npasses;
-    const int ib = P->idx_bits;
+    const int ks = P->key_shift;
+    const bool pair = P->pair_mode != 0;
     const double ox = P->ox, oy = P->oy, oz = P->oz, inv = P->inv_s;
     const int64_t NX = P->NX, NY = P->NY, NZ = P->NZ;
     const int by = P->by, bz = P->bz;
@@ -286,12 +292,13 @@ __global__ __launch_bounds__(kBlock) void k_keys(const float *__restrict__ xyz,
         } else {
             key = invalid_key;
         }
-        const uint64_t e = (key << ib) | (uint64_t)i;
+        const uint64_t e = pair ? key : ((key << ks) | (uint64_t)i);
         keys[i] = e;
+        if (pair) vals[i] = (uint32_t)i;
         const uint64_t act = __ballot(1);
         const int leader = first_lane(act);
         for (int p = 0; p < np; ++p) {
-            const uint32_t dg = (uint32_t)(e >> (ib + p * kRadixBits)) & (kRadix - 1);
+            const uint32_t dg = (uint32_t)(e >> (ks + p * kRadixBits)) & (kRadix - 1);
             const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
             if (__ballot(dg == d0) == act) {
                 if (lane == leader) atomicAdd(&sh[p][d0], (uint32_t)__popcll(act));
@@ -320,6 +327,8 @@ constexpr uint32_t kSpinLimit = 1u << 22;
 
 __global__ __launch_bounds__(kBlock) void k_sort_pass(const uint64_t *__restrict__ src,
                                                       uint64_t *__restrict__ dst,
+                                                      const uint32_t *__restrict__ srcv,
+                                                      uint32_t *__restrict__ dstv,
                                                       Params *__restrict__ P,
                                                       uint64_t *__restrict__ lb_cur,
                                                       uint64_t *__restrict__ lb_next, int pass,
@@ -342,7 +351,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(const uint64_t *__restrict
     }
     __syncthreads();
     const int64_t tile = s_tile;
-    const int shift = P->idx_bits + pass * kRadixBits;
+    const int shift = P->key_shift + pass * kRadixBits;
+    const bool pair = P->pair_mode != 0;
     const int64_t base = tile * kTile + (int64_t)wave * (64 * kItems);
 
     uint64_t v[kItems];
@@ -418,21 +428,26 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(const uint64_t *__restrict
     }
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        const bool valid = base + k * 64 + lane < n;
-        if (valid) {
+        const int64_t e = base + k * 64 + lane;
+        if (e < n) {
             const uint32_t dg = (uint32_t)(v[k] >> shift) & (kRadix - 1);
             const uint64_t pos = (uint64_t)s_base[dg] + s_cnt[wave][dg] + rk[k];
-            if (pos < (uint64_t)n) dst[pos] = v[k];
+            if (pos < (uint64_t)n) {
+                dst[pos] = v[k];
+                if (pair) dstv[pos] = srcv[e];
+            }
         }
     }
 }
 
 // ------------------------------------------------------------- 5. gather
-__device__ __forceinline__ bool cell_flag(const uint64_t *srt, int64_t e, int ib,
+// Sorted words: key = word >> key_shift; index = low bits (one-word mode)
+// or the parallel index array (pair mode).
+__device__ __forceinline__ bool cell_flag(const uint64_t *srt, int64_t e, int ks,
                                           uint64_t &key) {
     const uint64_t v = srt[e];
-    key = v >> ib;
-    return e == 0 || (srt[e - 1] >> ib) != key;
+    key = v >> ks;
+    return e == 0 || (srt[e - 1] >> ks) != key;
 }
 
 // Points in sorted order (x, y, z, original index bits), original indices,
@@ -440,14 +455,18 @@ __device__ __forceinline__ bool cell_flag(const uint64_t *srt, int64_t e, int ib
 __global__ __launch_bounds__(kBlock) void k_gather(const float *__restrict__ xyz,
                                                    const uint64_t *__restrict__ s0,
                                                    const uint64_t *__restrict__ s1,
+                                                   const uint32_t *__restrict__ v0,
+                                                   const uint32_t *__restrict__ v1,
                                                    Params *__restrict__ P,
                                                    float4 *__restrict__ spts,
                                                    uint32_t *__restrict__ sorig,
                                                    uint32_t *__restrict__ tile_cnt) {
     if (P->status != kStatusOk) return;
     const uint64_t *srt = (P->npasses & 1) ? s1 : s0;
+    const uint32_t *sv = (P->npasses & 1) ? v1 : v0;
     const int64_t n = P->n, nvalid = P->nvalid;
-    const int ib = P->idx_bits, bz = P->bz;
+    const int ks = P->key_shift, bz = P->bz;
+    const bool pair = P->pair_mode != 0;
     const uint64_t mask = P->idx_mask;
     const int64_t base = (int64_t)blockIdx.x * kTile;
     uint32_t nc = 0, ncol = 0;
@@ -456,7 +475,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(const float *__restrict__ xyz
         const int64_t e = base + k * kBlock + threadIdx.x;
         if (e < n) {
             const uint64_t v = srt[e];
-            uint32_t i = (uint32_t)(v & mask);
+            uint32_t i = pair ? sv[e] : (uint32_t)(v & mask);
             if (i >= (uint64_t)n) {  // cannot happen for a correct sort; never read out of range
                 atomicExch(&P->status, kStatusDevice);
                 i = 0;
@@ -466,8 +485,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(const float *__restrict__ xyz
             spts[e] = make_float4(x, y, z, __uint_as_float(i));
             sorig[e] = i;
             if (e < nvalid) {
-                const uint64_t key = v >> ib;
-                const uint64_t pk = e > 0 ? (srt[e - 1] >> ib) : ~0ull;
+                const uint64_t key = v >> ks;
+                const uint64_t pk = e > 0 ? (srt[e - 1] >> ks) : ~0ull;
                 if (e == 0 || pk != key) {
                     ++nc;
                     if (e == 0 || (pk >> bz) != (key >> bz)) ++ncol;
@@ -526,138 +545,125 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const uint32_t *__restrict__
             P->M = 0;
             P->Mcol = 0;
         }
-        uint64_t cap = 64;
-        while (cap < 2ull * s_b[1023]) cap <<= 1;
-        P->hmask = cap - 1;
     }
 }
 
-// ------------------------------------------------------------- 7. hash clear
-__global__ __launch_bounds__(kBlock) void k_hash_clear(uint64_t *__restrict__ hkeys,
-                                                       const Params *__restrict__ P) {
-    if (P->status != kStatusOk) return;
-    const uint64_t cap = P->hmask + 1;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < cap;
-         i += (uint64_t)gridDim.x * kBlock)
-        hkeys[i] = kHashEmpty;
-}
-
-// ------------------------------------------------------------- 8. cells
-// Cell table: first sorted position and key of every occupied cell, and the
-// per-cell union-find / size / id slots.
+// ------------------------------------------------------------- 7. cells
+// Cell table (first sorted position and key of every occupied cell, and
+// its column) and column table (key (cx, cy) and first cell of every
+// occupied column), plus the per-cell union-find / size / id slots.
 __global__ __launch_bounds__(kBlock) void k_cells(const uint64_t *__restrict__ s0,
                                                   const uint64_t *__restrict__ s1,
                                                   const Params *__restrict__ P,
                                                   const uint32_t *__restrict__ tile_off,
                                                   uint32_t *__restrict__ cell_start,
                                                   uint64_t *__restrict__ cell_key,
+                                                  uint32_t *__restrict__ cell_col,
+                                                  uint64_t *__restrict__ col_key,
+                                                  uint32_t *__restrict__ col_cell,
                                                   int32_t *__restrict__ cpar,
                                                   uint32_t *__restrict__ csize,
                                                   uint32_t *__restrict__ ccanon) {
     if (P->status != kStatusOk) return;
     const uint64_t *srt = (P->npasses & 1) ? s1 : s0;
     const int64_t nvalid = P->nvalid;
-    const int ib = P->idx_bits;
+    const int ks = P->key_shift, bz = P->bz;
     const int64_t base = (int64_t)blockIdx.x * kTile;
     const int wave = threadIdx.x >> 6, lane = __lane_id();
     __shared__ uint32_t s_tot[kItems][kBlock / 64];
-    uint32_t flags = 0;
+    __shared__ uint32_t s_ctot[kItems][kBlock / 64];
+    uint32_t flags = 0, cflags = 0;
     for (int k = 0; k < kItems; ++k) {
         const int64_t e = base + k * kBlock + threadIdx.x;
-        uint64_t key;
-        const bool f = e < nvalid && cell_flag(srt, e, ib, key);
+        uint64_t key = 0;
+        const bool f = e < nvalid && cell_flag(srt, e, ks, key);
+        const bool cf = f && (e == 0 || ((srt[e - 1] >> ks) >> bz) != (key >> bz));
         flags |= (uint32_t)f << k;
-        const uint64_t m = __ballot(f);
-        if (lane == 0) s_tot[k][wave] = (uint32_t)__popcll(m);
+        cflags |= (uint32_t)cf << k;
+        const uint64_t m = __ballot(f), mc = __ballot(cf);
+        if (lane == 0) {
+            s_tot[k][wave] = (uint32_t)__popcll(m);
+            s_ctot[k][wave] = (uint32_t)__popcll(mc);
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t run = 0;
+        uint32_t run = 0, crun = 0;
         for (int k = 0; k < kItems; ++k)
             for (int w = 0; w < kBlock / 64; ++w) {
-                const uint32_t t = s_tot[k][w];
+                const uint32_t t = s_tot[k][w], c = s_ctot[k][w];
                 s_tot[k][w] = run;
+                s_ctot[k][w] = crun;
                 run += t;
+                crun += c;
             }
     }
     __syncthreads();
-    const uint32_t c0 = tile_off[2 * blockIdx.x];
+    const uint32_t c0 = tile_off[2 * blockIdx.x], q0 = tile_off[2 * blockIdx.x + 1];
+    const uint64_t lt = lanemask_lt();
     for (int k = 0; k < kItems; ++k) {
-        const bool f = (flags >> k) & 1u;
-        const uint64_t m = __ballot(f);
+        const bool f = (flags >> k) & 1u, cf = (cflags >> k) & 1u;
+        const uint64_t m = __ballot(f), mc = __ballot(cf);
         if (f) {
             const int64_t e = base + k * kBlock + threadIdx.x;
-            const uint32_t cid = c0 + s_tot[k][wave] + (uint32_t)__popcll(m & lanemask_lt());
+            const uint32_t cid = c0 + s_tot[k][wave] + (uint32_t)__popcll(m & lt);
+            const uint32_t colx = q0 + s_ctot[k][wave] + (uint32_t)__popcll(mc & lt);
             if ((int64_t)cid >= nvalid) continue;
+            const uint64_t key = srt[e] >> ks;
             cell_start[cid] = (uint32_t)e;
-            cell_key[cid] = srt[e] >> ib;
+            cell_key[cid] = key;
+            cell_col[cid] = cf ? colx : colx - 1;
             cpar[cid] = (int32_t)cid;
             csize[cid] = 0;
             ccanon[cid] = 0xFFFFFFFFu;
-        }
-    }
-}
-
-// ------------------------------------------------------------- 9. columns
-__device__ __forceinline__ uint64_t col_hash(uint64_t c) {
-    uint64_t h = c * 0x9E3779B97F4A7C15ull;
-    return h ^ (h >> 31);
-}
-
-// Inserts every occupied column (cx, cy) -> (first cell, number of cells).
-__global__ __launch_bounds__(kBlock) void k_columns(const uint64_t *__restrict__ cell_key,
-                                                    uint32_t *__restrict__ cell_start,
-                                                    uint64_t *__restrict__ hkeys,
-                                                    uint64_t *__restrict__ hvals,
-                                                    Params *__restrict__ P) {
-    if (P->status != kStatusOk) return;
-    const int64_t M = P->M;
-    const int bz = P->bz;
-    const uint64_t hmask = P->hmask;
-    if (blockIdx.x == 0 && threadIdx.x == 0) cell_start[M] = (uint32_t)P->nvalid;
-    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < M;
-         c += (int64_t)gridDim.x * kBlock) {
-        const uint64_t col = cell_key[c] >> bz;
-        if (c > 0 && (cell_key[c - 1] >> bz) == col) continue;
-        int64_t e = c + 1;
-        while (e < M && (cell_key[e] >> bz) == col) ++e;
-        const uint64_t val = ((uint64_t)c << 32) | (uint64_t)(e - c);
-        uint64_t slot = col_hash(col) & hmask;
-        bool done = false;
-        for (uint64_t probe = 0; probe <= hmask; ++probe) {
-            const uint64_t prev = atomicCAS((unsigned long long *)&hkeys[slot],
-                                            (unsigned long long)kHashEmpty,
-                                            (unsigned long long)col);
-            if (prev == kHashEmpty || prev == col) {
-                hvals[slot] = val;
-                done = true;
-                break;
+            if (cf) {
+                col_key[colx] = key >> bz;
+                col_cell[colx] = cid;
             }
-            slot = (slot + 1) & hmask;
         }
-        if (!done) atomicExch(&P->status, kStatusDevice);
     }
 }
 
-__device__ __forceinline__ bool col_lookup(const uint64_t *__restrict__ hkeys,
-                                           const uint64_t *__restrict__ hvals, uint64_t hmask,
-                                           uint64_t col, uint32_t &first, uint32_t &count) {
-    uint64_t slot = col_hash(col) & hmask;
-    for (uint64_t probe = 0; probe <= hmask; ++probe) {
-        const uint64_t k = hkeys[slot];
-        if (k == col) {
-            const uint64_t v = hvals[slot];
-            first = (uint32_t)(v >> 32);
-            count = (uint32_t)v;
-            return true;
-        }
-        if (k == kHashEmpty) return false;
-        slot = (slot + 1) & hmask;
+// ------------------------------------------------------------- 8. column rows
+// For every column (cx, cy), the first column of rows cx+1 and cx+2 whose
+// cy' >= cy - 2 (columns are sorted by (cx, cy), so the columns of the
+// stencil in one row are consecutive from there).
+__global__ __launch_bounds__(kBlock) void k_colrows(const uint64_t *__restrict__ col_key,
+                                                    uint32_t *__restrict__ col_cell,
+                                                    uint32_t *__restrict__ cell_start,
+                                                    uint32_t *__restrict__ row_start,
+                                                    const Params *__restrict__ P) {
+    if (P->status != kStatusOk) return;
+    const int64_t Mcol = P->Mcol;
+    const int by = P->by;
+    const uint64_t ymask = (1ull << by) - 1;
+    const int64_t NX = P->NX;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        col_cell[Mcol] = (uint32_t)P->M;
+        cell_start[P->M] = (uint32_t)P->nvalid;
     }
-    return false;
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < Mcol;
+         c += (int64_t)gridDim.x * kBlock) {
+        const uint64_t ck = col_key[c];
+        const uint64_t cx = ck >> by, cy = ck & ymask;
+        for (int dx = 1; dx <= 2; ++dx) {
+            uint32_t rs = (uint32_t)Mcol;
+            if ((int64_t)(cx + dx) < NX) {
+                const uint64_t target = ((cx + dx) << by) | (cy >= 2 ? cy - 2 : 0);
+                uint32_t lo = (uint32_t)c + 1, hi = (uint32_t)Mcol;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (col_key[mid] < target) lo = mid + 1;
+                    else hi = mid;
+                }
+                rs = lo;
+            }
+            row_start[2 * c + dx - 1] = rs;
+        }
+    }
 }
 
-// ------------------------------------------------------------- 10. hooking
+// ------------------------------------------------------------- 9. hooking
 // Union-find over cells; parent[x] <= x always, roots are the smallest cell
 // of their component.
 __device__ __forceinline__ int32_t uf_find(int32_t *par, int32_t x) {
@@ -695,16 +701,6 @@ __device__ __forceinline__ void uf_link(int32_t *par, int32_t a, int32_t b) {
     }
 }
 
-struct ColOffset {
-    int8_t dx, dy, near;  // near: this column is also in the near shell
-};
-
-// Forward neighbour columns of the two shells (dx > 0, or dx == 0 and dy > 0).
-__constant__ ColOffset kNearCols[4] = {{0, 1, 1}, {1, -1, 1}, {1, 0, 1}, {1, 1, 1}};
-__constant__ ColOffset kFarCols[12] = {{0, 1, 1},  {0, 2, 0},  {1, -2, 0}, {1, -1, 1},
-                                       {1, 0, 1},  {1, 1, 1},  {1, 2, 0},  {2, -2, 0},
-                                       {2, -1, 0}, {2, 0, 0},  {2, 1, 0},  {2, 2, 0}};
-
 // Tests the cell pair (A, B) point pair by point pair until the first
 // joined pair; joins their components when one is found.  Skips pairs that
 // already share a root.
@@ -727,59 +723,80 @@ __device__ __forceinline__ void hook_pair(int32_t A, int32_t B, uint32_t sA, uin
     }
 }
 
+// One shell of the forward half of the 5x5x5 stencil around every cell.
+// ROUND 0 (near): offsets with max(|dx|,|dy|,|dz|) = 1.
+// ROUND 1 (far):  offsets with max(|dx|,|dy|,|dz|) = 2.
+// Forward: dx > 0, or dx == 0 and dy > 0, or dx == dy == 0 and dz > 0.
 template <int ROUND>
 __global__ __launch_bounds__(kBlock) void k_hook(const float4 *__restrict__ spts,
                                                  const uint32_t *__restrict__ cell_start,
                                                  const uint64_t *__restrict__ cell_key,
-                                                 int32_t *cpar,
-                                                 const uint64_t *__restrict__ hkeys,
-                                                 const uint64_t *__restrict__ hvals,
-                                                 const Params *__restrict__ P) {
+                                                 const uint32_t *__restrict__ cell_col,
+                                                 const uint64_t *__restrict__ col_key,
+                                                 const uint32_t *__restrict__ col_cell,
+                                                 const uint32_t *__restrict__ row_start,
+                                                 int32_t *cpar, const Params *__restrict__ P) {
     if (P->status != kStatusOk) return;
-    const int64_t M = P->M;
+    const int64_t M = P->M, Mcol = P->Mcol;
     const float d2 = P->d2;
     const int by = P->by, bz = P->bz;
-    const int64_t NX = P->NX, NY = P->NY;
     const uint64_t zmask = (1ull << bz) - 1, ymask = (1ull << by) - 1;
-    const uint64_t hmask = P->hmask;
-    const int zr = ROUND == 0 ? 1 : 2;
+    constexpr int zr = ROUND == 0 ? 1 : 2;
     for (int64_t Ai = (int64_t)blockIdx.x * kBlock + threadIdx.x; Ai < M;
          Ai += (int64_t)gridDim.x * kBlock) {
         const int32_t A = (int32_t)Ai;
         const uint64_t key = cell_key[A];
         const int64_t cz = (int64_t)(key & zmask);
-        const int64_t cy = (int64_t)((key >> bz) & ymask);
-        const int64_t cx = (int64_t)(key >> (bz + by));
+        const uint64_t ck = key >> bz;
+        const int64_t cx = (int64_t)(ck >> by), cy = (int64_t)(ck & ymask);
+        const uint32_t col = cell_col[A];
         const uint32_t sA = cell_start[A], eA = cell_start[A + 1];
-        // own column, cells above: dz = +1 (near) or +2 (far)
+
+        auto scan_column = [&](uint32_t c2, int64_t dx, int64_t dy) {
+            const bool near_col = dx <= 1 && dy <= 1 && dy >= -1;
+            const uint32_t b0 = col_cell[c2], b1 = col_cell[c2 + 1];
+            uint32_t lo = b0, hi = b1;
+            if (b1 - b0 > 8) {  // first cell with cz' >= cz - zr
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if ((int64_t)(cell_key[mid] & zmask) < cz - zr) lo = mid + 1;
+                    else hi = mid;
+                }
+            }
+            for (uint32_t B = lo; B < b1; ++B) {
+                const int64_t dz = (int64_t)(cell_key[B] & zmask) - cz;
+                if (dz < -zr) continue;
+                if (dz > zr) break;
+                if (ROUND == 1 && near_col && dz >= -1 && dz <= 1) continue;
+                hook_pair(A, (int32_t)B, sA, eA, spts, cell_start, cpar, d2);
+            }
+        };
+
+        // own column, cells above: dz = +zr
         for (int32_t B = A + 1; B < M && B <= A + 2; ++B) {
             const uint64_t kb = cell_key[B];
-            if ((kb >> bz) != (key >> bz)) break;
+            if ((kb >> bz) != ck) break;
             const int64_t dz = (int64_t)(kb & zmask) - cz;
             if (dz > zr) break;
             if (dz == zr) hook_pair(A, B, sA, eA, spts, cell_start, cpar, d2);
         }
-        const int ncols = ROUND == 0 ? 4 : 12;
-        for (int c = 0; c < ncols; ++c) {
-            const ColOffset o = ROUND == 0 ? kNearCols[c] : kFarCols[c];
-            const int64_t nx = cx + o.dx, ny = cy + o.dy;
-            if (nx >= NX || ny < 0 || ny >= NY) continue;
-            uint32_t first, count;
-            if (!col_lookup(hkeys, hvals, hmask, ((uint64_t)nx << by) | (uint64_t)ny, first,
-                            count))
-                continue;
-            const int64_t zlo = cz - zr;
-            uint32_t lo = first, hi = first + count;
-            while (lo < hi) {  // first cell of the column with z >= zlo
-                const uint32_t mid = (lo + hi) >> 1;
-                if ((int64_t)(cell_key[mid] & zmask) < zlo) lo = mid + 1;
-                else hi = mid;
-            }
-            for (uint32_t B = lo; B < first + count; ++B) {
-                const int64_t dz = (int64_t)(cell_key[B] & zmask) - cz;
-                if (dz > zr) break;
-                if (ROUND == 1 && o.near && dz >= -1 && dz <= 1) continue;
-                hook_pair(A, (int32_t)B, sA, eA, spts, cell_start, cpar, d2);
+        // row dx = 0: columns cy+1 .. cy+zr follow this column directly
+        for (uint32_t c2 = col + 1; c2 <= col + zr && (int64_t)c2 < Mcol; ++c2) {
+            const uint64_t k2 = col_key[c2];
+            if ((int64_t)(k2 >> by) != cx) break;
+            const int64_t dy = (int64_t)(k2 & ymask) - cy;
+            if (dy > zr) break;
+            scan_column(c2, 0, dy);
+        }
+        // rows dx = 1 (and 2 in the far shell)
+        for (int dx = 1; dx <= zr; ++dx) {
+            for (uint32_t c2 = row_start[2 * col + dx - 1]; (int64_t)c2 < Mcol; ++c2) {
+                const uint64_t k2 = col_key[c2];
+                if ((int64_t)(k2 >> by) != cx + dx) break;
+                const int64_t dy = (int64_t)(k2 & ymask) - cy;
+                if (dy > zr) break;
+                if (dy < -zr) continue;
+                scan_column(c2, dx, dy);
             }
         }
     }
@@ -797,9 +814,14 @@ __global__ __launch_bounds__(kBlock) void k_compress(int32_t *cpar, const Params
     }
 }
 
-// ------------------------------------------------------------- 11. finalize
-// Cluster sizes and smallest original index per root, aggregated per wave
-// and per block (one root of a giant component takes most cells).
+// ------------------------------------------------------------- 10. finalize
+// Cluster sizes and smallest original index per root.  Each block takes a
+// contiguous run of cells and adds them into a block-local hash table of
+// roots in LDS (one root of a giant component takes most cells, and global
+// atomics on one address serialise), then flushes one global atomic per
+// distinct root.
+constexpr int kAggSlots = 4096;
+
 __global__ __launch_bounds__(kBlock) void k_final_cells(const int32_t *__restrict__ cpar,
                                                         const uint32_t *__restrict__ cell_start,
                                                         const uint32_t *__restrict__ sorig,
@@ -807,22 +829,41 @@ __global__ __launch_bounds__(kBlock) void k_final_cells(const int32_t *__restric
                                                         uint32_t *__restrict__ ccanon,
                                                         Params *__restrict__ P) {
     if (P->status != kStatusOk) return;
-    __shared__ int32_t s_root;
-    __shared__ uint32_t s_sum, s_min, s_max;
-    if (threadIdx.x == 0) {
-        s_root = -1;
-        s_sum = 0;
-        s_min = 0xFFFFFFFFu;
-        s_max = 0;
+    __shared__ int32_t t_key[kAggSlots];
+    __shared__ uint32_t t_sum[kAggSlots], t_min[kAggSlots];
+    __shared__ uint32_t s_max;
+    for (int i = threadIdx.x; i < kAggSlots; i += kBlock) {
+        t_key[i] = -1;
+        t_sum[i] = 0;
+        t_min[i] = 0xFFFFFFFFu;
     }
+    if (threadIdx.x == 0) s_max = 0;
     __syncthreads();
     const int64_t M = P->M;
+    const int64_t per = (M + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * per;
+    const int64_t hi = lo + per < M ? lo + per : M;
     const int lane = __lane_id();
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
     uint32_t cmax = 0;
-    for (int64_t b0 = (int64_t)blockIdx.x * kBlock; b0 < M; b0 += stride) {
+
+    auto add = [&](int32_t r, uint32_t c, uint32_t m) {
+        uint32_t h = ((uint32_t)r * 2654435761u) >> (32 - 12);
+        for (int probe = 0; probe < 64; ++probe) {
+            const int32_t prev = atomicCAS(&t_key[h], -1, r);
+            if (prev == -1 || prev == r) {
+                atomicAdd(&t_sum[h], c);
+                atomicMin(&t_min[h], m);
+                return;
+            }
+            h = (h + 1) & (kAggSlots - 1);
+        }
+        atomicAdd(&csize[r], c);  // table crowded: go straight to memory
+        atomicMin(&ccanon[r], m);
+    };
+
+    for (int64_t b0 = lo; b0 < hi; b0 += kBlock) {
         const int64_t A = b0 + threadIdx.x;
-        const bool valid = A < M;
+        const bool valid = A < hi;
         int32_t r = -1;
         uint32_t cnt = 0, mn = 0xFFFFFFFFu;
         if (valid) {
@@ -842,31 +883,22 @@ __global__ __launch_bounds__(kBlock) void k_final_cells(const int32_t *__restric
         if (__ballot(valid && r == r0) == act) {
             const uint32_t c = wave_sum(cnt);
             const uint32_t m = wave_min_u32(mn);
-            if (lane == leader) {
-                const int32_t cur = atomicCAS(&s_root, -1, r0);
-                if (cur == -1 || cur == r0) {
-                    atomicAdd(&s_sum, c);
-                    atomicMin(&s_min, m);
-                } else {
-                    atomicAdd(&csize[r0], c);
-                    atomicMin(&ccanon[r0], m);
-                }
-            }
+            if (lane == leader) add(r0, c, m);
         } else if (valid) {
-            atomicAdd(&csize[r], cnt);
-            atomicMin(&ccanon[r], mn);
+            add(r, cnt, mn);
         }
     }
     cmax = wave_max_u32(cmax);
     if (lane == 0) atomicMax(&s_max, cmax);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        if (s_root >= 0) {
-            atomicAdd(&csize[s_root], s_sum);
-            atomicMin(&ccanon[s_root], s_min);
+    for (int i = threadIdx.x; i < kAggSlots; i += kBlock) {
+        const int32_t r = t_key[i];
+        if (r >= 0) {
+            atomicAdd(&csize[r], t_sum[i]);
+            atomicMin(&ccanon[r], t_min[i]);
         }
-        atomicMax(&P->max_cell, (int32_t)s_max);
     }
+    if (threadIdx.x == 0) atomicMax(&P->max_cell, (int32_t)s_max);
 }
 
 // Labels in the caller's order and the number of kept clusters.
@@ -926,16 +958,10 @@ __global__ void k_finish(const Params *__restrict__ P, int32_t *__restrict__ k_o
 
 const char *stage_name(int s) {
     static const char *names[kNumStages] = {
-        "bbox",      "plan",       "keys",      "sort_pass",  "gather",      "tile_scan",
-        "hash_clear", "cells",     "columns",   "hook_near",  "compress_1",  "hook_far",
-        "compress_2", "final_cells", "final_labels", "finish"};
+        "bbox",      "plan",       "keys",        "sort_pass",    "gather",
+        "tile_scan", "cells",      "column_rows", "hook_near",    "compress_1",
+        "hook_far",  "compress_2", "final_cells", "final_labels", "finish"};
     return (s >= 0 && s < kNumStages) ? names[s] : "";
-}
-
-static inline int host_bits_for(int64_t v) {
-    int b = 0;
-    while (b < 63 && (1ll << b) < v) ++b;
-    return b;
 }
 
 hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_size,
@@ -948,6 +974,8 @@ hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_siz
     uint32_t *tile_off = reinterpret_cast<uint32_t *>(w + L.tile_off);
     uint64_t *keys0 = reinterpret_cast<uint64_t *>(w + L.keys0);
     uint64_t *keys1 = reinterpret_cast<uint64_t *>(w + L.keys1);
+    uint32_t *vals0 = reinterpret_cast<uint32_t *>(w + L.vals0);
+    uint32_t *vals1 = reinterpret_cast<uint32_t *>(w + L.vals1);
     uint64_t *lb0 = reinterpret_cast<uint64_t *>(w + L.lb0);
     uint64_t *lb1 = reinterpret_cast<uint64_t *>(w + L.lb1);
     float4 *spts = reinterpret_cast<float4 *>(w + L.spts);
@@ -957,8 +985,10 @@ hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_siz
     int32_t *cpar = reinterpret_cast<int32_t *>(w + L.cpar);
     uint32_t *csize = reinterpret_cast<uint32_t *>(w + L.csize);
     uint32_t *ccanon = reinterpret_cast<uint32_t *>(w + L.ccanon);
-    uint64_t *hkeys = reinterpret_cast<uint64_t *>(w + L.hkeys);
-    uint64_t *hvals = reinterpret_cast<uint64_t *>(w + L.hvals);
+    uint32_t *cell_col = reinterpret_cast<uint32_t *>(w + L.cell_col);
+    uint64_t *col_key = reinterpret_cast<uint64_t *>(w + L.col_key);
+    uint32_t *col_cell = reinterpret_cast<uint32_t *>(w + L.col_cell);
+    uint32_t *row_start = reinterpret_cast<uint32_t *>(w + L.row_start);
 
     const int64_t ntiles = L.ntiles;
     int nb_bbox = (int)((n + kBlock * 4 - 1) / (kBlock * 4));
@@ -966,11 +996,9 @@ hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_siz
     int64_t nb_pts = (n + kBlock - 1) / kBlock;
     const int nb_stream = (int)(nb_pts > 8192 ? 8192 : (nb_pts < 1 ? 1 : nb_pts));
     const int nb_cells = (int)(nb_pts > kCellBlocks ? kCellBlocks : (nb_pts < 1 ? 1 : nb_pts));
-    const uint64_t hb = L.hcap_max / kBlock;
-    const int nb_hash = (int)(hb > 8192 ? 8192 : (hb < 1 ? 1 : hb));
-    int ib_host = host_bits_for(n);
-    if (ib_host < 1) ib_host = 1;
-    const int max_passes = (64 - ib_host + kRadixBits - 1) / kRadixBits;
+    // Passes beyond the device-side count return at once; the pair-mode
+    // fallback can need up to a full 64-bit key.
+    const int max_passes = kMaxPasses;
 
 #define FEC_LAUNCH(stage, ...)                         \
     do {                                               \
@@ -984,30 +1012,33 @@ hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_siz
     FEC_LAUNCH(kStBbox, k_bbox<<<nb_bbox, kBlock, 0, st>>>(xyz, n, partials));
     FEC_LAUNCH(kStPlan, k_plan<<<1, kBlock, 0, st>>>(partials, nb_bbox, P, n, d, min_size,
                                                       max_size));
-    FEC_LAUNCH(kStKeys, k_keys<<<nb_stream, kBlock, 0, st>>>(xyz, P, keys0, lb0,
+    FEC_LAUNCH(kStKeys, k_keys<<<nb_stream, kBlock, 0, st>>>(xyz, P, keys0, vals0, lb0,
                                                               ntiles * kRadix));
     for (int pass = 0; pass < max_passes; ++pass) {
         const uint64_t *src = (pass & 1) ? keys1 : keys0;
         uint64_t *dst = (pass & 1) ? keys0 : keys1;
+        const uint32_t *srcv = (pass & 1) ? vals1 : vals0;
+        uint32_t *dstv = (pass & 1) ? vals0 : vals1;
         uint64_t *cur = (pass & 1) ? lb1 : lb0;
         uint64_t *nxt = (pass & 1) ? lb0 : lb1;
         FEC_LAUNCH(kStSort, k_sort_pass<<<(unsigned)ntiles, kBlock, 0, st>>>(
-                                src, dst, P, cur, nxt, pass, n, ntiles));
+                                src, dst, srcv, dstv, P, cur, nxt, pass, n, ntiles));
     }
     FEC_LAUNCH(kStGather, k_gather<<<(unsigned)ntiles, kBlock, 0, st>>>(
-                              xyz, keys0, keys1, P, spts, sorig, tile_cnt));
+                              xyz, keys0, keys1, vals0, vals1, P, spts, sorig, tile_cnt));
     FEC_LAUNCH(kStTileScan, k_tile_scan<<<1, 1024, 0, st>>>(tile_cnt, tile_off, ntiles, P));
-    FEC_LAUNCH(kStHashClear, k_hash_clear<<<nb_hash, kBlock, 0, st>>>(hkeys, P));
     FEC_LAUNCH(kStCells, k_cells<<<(unsigned)ntiles, kBlock, 0, st>>>(
-                             keys0, keys1, P, tile_off, cell_start, cell_key, cpar, csize,
-                             ccanon));
-    FEC_LAUNCH(kStColumns, k_columns<<<nb_cells, kBlock, 0, st>>>(cell_key, cell_start, hkeys,
-                                                                   hvals, P));
-    FEC_LAUNCH(kStHookNear, k_hook<0><<<nb_cells, kBlock, 0, st>>>(spts, cell_start, cell_key,
-                                                                    cpar, hkeys, hvals, P));
+                             keys0, keys1, P, tile_off, cell_start, cell_key, cell_col, col_key,
+                             col_cell, cpar, csize, ccanon));
+    FEC_LAUNCH(kStColumnRows, k_colrows<<<nb_cells, kBlock, 0, st>>>(col_key, col_cell,
+                                                                      cell_start, row_start, P));
+    FEC_LAUNCH(kStHookNear, k_hook<0><<<nb_cells, kBlock, 0, st>>>(
+                                spts, cell_start, cell_key, cell_col, col_key, col_cell,
+                                row_start, cpar, P));
     FEC_LAUNCH(kStCompress1, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P));
-    FEC_LAUNCH(kStHookFar, k_hook<1><<<nb_cells, kBlock, 0, st>>>(spts, cell_start, cell_key,
-                                                                   cpar, hkeys, hvals, P));
+    FEC_LAUNCH(kStHookFar, k_hook<1><<<nb_cells, kBlock, 0, st>>>(
+                               spts, cell_start, cell_key, cell_col, col_key, col_cell,
+                               row_start, cpar, P));
     FEC_LAUNCH(kStCompress2, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P));
     FEC_LAUNCH(kStFinalCells, k_final_cells<<<nb_cells, kBlock, 0, st>>>(
                                   cpar, cell_start, sorig, csize, ccanon, P));

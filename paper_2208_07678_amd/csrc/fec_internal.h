@@ -22,8 +22,6 @@ constexpr uint64_t kLbAggregate = 1ull << 62;
 constexpr uint64_t kLbInclusive = 2ull << 62;
 constexpr uint64_t kLbValue = (1ull << 62) - 1;
 
-constexpr uint64_t kHashEmpty = ~0ull;
-
 // Device-side status values (mirror the public FEC_* codes).
 constexpr int32_t kStatusOk = 0;
 constexpr int32_t kStatusRange = -2;
@@ -47,10 +45,11 @@ struct Params {
     int32_t key_bits;     // bits sorted (grid key, plus one for non-finite points)
     int32_t idx_bits;     // bits of the point index packed below the key
     int32_t npasses;      // radix passes actually run
+    int32_t pair_mode;    // 0: one word (key << idx_bits | index); 1: key and index arrays
+    int32_t key_shift;    // idx_bits in one-word mode, 0 in pair mode
     uint64_t idx_mask;
     int64_t M;            // occupied cells
     int64_t Mcol;         // occupied columns (cells sharing cx, cy)
-    uint64_t hmask;       // column hash capacity - 1
     int32_t kept;         // kept clusters
     int32_t max_cell;     // largest number of points in one cell
     uint32_t ticket[kMaxPasses];
@@ -60,12 +59,11 @@ struct Params {
 // ---------------------------------------------------------------- workspace
 struct Layout {
     size_t params, partials, tile_cnt, tile_off;
-    size_t keys0, keys1, lb0, lb1;
+    size_t keys0, keys1, vals0, vals1, lb0, lb1;
     size_t spts, sorig, cell_start, cell_key, cpar, csize, ccanon;
-    size_t hkeys, hvals;
+    size_t cell_col, col_key, col_cell, row_start;
     size_t total;
     int64_t ntiles;
-    uint64_t hcap_max;
 };
 
 inline uint64_t next_pow2(uint64_t v) {
@@ -87,13 +85,14 @@ inline Layout make_layout(int64_t n) {
     };
     const size_t un = (size_t)(n > 0 ? n : 1);
     L.ntiles = (int64_t)((un + kTile - 1) / kTile);
-    L.hcap_max = next_pow2(2 * un < 64 ? 64 : 2 * un);
     L.params = take(sizeof(Params));
     L.partials = take((size_t)kBboxBlocks * 8 * sizeof(float));
     L.tile_cnt = take((size_t)L.ntiles * 2 * sizeof(uint32_t));
     L.tile_off = take((size_t)L.ntiles * 2 * sizeof(uint32_t));
     L.keys0 = take(un * sizeof(uint64_t));
     L.keys1 = take(un * sizeof(uint64_t));
+    L.vals0 = take(un * sizeof(uint32_t));
+    L.vals1 = take(un * sizeof(uint32_t));
     L.lb0 = take((size_t)L.ntiles * kRadix * sizeof(uint64_t));
     L.lb1 = take((size_t)L.ntiles * kRadix * sizeof(uint64_t));
     L.spts = take(un * sizeof(float4));
@@ -103,8 +102,10 @@ inline Layout make_layout(int64_t n) {
     L.cpar = take(un * sizeof(int32_t));
     L.csize = take(un * sizeof(int32_t));
     L.ccanon = take(un * sizeof(int32_t));
-    L.hkeys = take((size_t)L.hcap_max * sizeof(uint64_t));
-    L.hvals = take((size_t)L.hcap_max * sizeof(uint64_t));
+    L.cell_col = take(un * sizeof(uint32_t));
+    L.col_key = take(un * sizeof(uint64_t));
+    L.col_cell = take((un + 1) * sizeof(uint32_t));
+    L.row_start = take(2 * un * sizeof(uint32_t));
     L.total = off;
     return L;
 }
@@ -117,9 +118,8 @@ enum Stage : int {
     kStSort,
     kStGather,
     kStTileScan,
-    kStHashClear,
     kStCells,
-    kStColumns,
+    kStColumnRows,
     kStHookNear,
     kStCompress1,
     kStHookFar,

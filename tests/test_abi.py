@@ -42,7 +42,7 @@ def test_workspace_bytes_linear(fec):
     assert fec.workspace_bytes(0) == 0
     assert fec.workspace_bytes(-5) == 0
     a, b = fec.workspace_bytes(1_000_000), fec.workspace_bytes(2_000_000)
-    assert 60 * 1_000_000 < a < 200 * 1_000_000
+    assert 60 * 1_000_000 < a < 200 * 1_000_000, a
     assert b > a
 
 

@@ -115,6 +115,16 @@ def test_degenerate_inputs():
     _check(c, float(np.nextafter(np.float32(0.25), np.float32(1))), 1, 10000, "chain above d")
 
 
+def test_wide_grid_pair_mode():
+    # grid key + point index exceed 64 bits: keys and indices sorted as pairs
+    rng = np.random.default_rng(8)
+    centres = rng.uniform(0, 100, size=(500, 3))
+    x = (np.repeat(centres, 10, axis=0) + rng.uniform(-3e-4, 3e-4, size=(5000, 3)))
+    x = x.astype(np.float32)[rng.permutation(5000)]
+    _check(x, 1e-3, 1, 5000, "wide grid, d=1e-3 over 100 m")
+    _check(x, 1e-3, 10, 10, "wide grid, size filter")
+
+
 def test_repeatable_bitwise():
     xyz, d, mn, mx = synth.make_config("lidar120k")
     first, k = gpu_cluster(xyz, d, mn, mx)
