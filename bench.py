@@ -183,7 +183,8 @@ def main():
         "config": {"workload": args.workload, "n_points": n, "d": d, "min_size": mn,
                    "max_size": mx, "clusters_kept": k, "cells": stats.get("cells"),
                    "max_points_per_cell": stats.get("max_points_per_cell"),
-                   "radix_passes": stats.get("radix_passes")},
+                   "radix_passes": stats.get("radix_passes"),
+                   "work_cells": stats.get("work_cells")},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

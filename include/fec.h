@@ -104,8 +104,11 @@ const char *fec_version(void);
  * Diagnostics of the last call that used `workspace` (waits for `stream`):
  * out[0] n, out[1] finite points, out[2] occupied grid cells, out[3] occupied
  * grid columns, out[4] grid key bits, out[5] radix passes, out[6..8] grid
- * cells along x, y, z, out[9] largest points per cell, out[10] status.
- * Writes min(max_out, 11) values; returns that count or a negative status.
+ * cells along x, y, z, out[9] largest points per cell, out[10] status,
+ * out[11] cells left outside the largest component by the sampling phase,
+ * out[12] that component's root cell, out[13..20] diagnostic event counts
+ * (zero unless the library was built with FEC_COUNTERS defined).
+ * Writes min(max_out, 21) values; returns that count or a negative status.
  */
 int32_t fec_workspace_stats(const void *workspace, void *stream, int64_t *out, int32_t max_out);
 

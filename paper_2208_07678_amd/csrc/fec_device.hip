@@ -37,6 +37,13 @@ namespace fec {
 
 // ------------------------------------------------------------------ helpers
 
+// Diagnostic event counts, compiled in with -DFEC_COUNTERS only.
+#ifdef FEC_COUNTERS
+#define FEC_COUNT(P, i, v) atomicAdd(&((Params *)(P))->counters[i], (unsigned long long)(v))
+#else
+#define FEC_COUNT(P, i, v) ((void)0)
+#endif
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const unsigned l = __lane_id();
     return l ? (~0ull >> (64 - l)) : 0ull;
@@ -171,7 +178,8 @@ __global__ __launch_bounds__(kBlock) void k_bbox(const float *__restrict__ xyz, 
 // number of radix passes.  One block.
 __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ partials, int nparts,
                                                  Params *__restrict__ P, int64_t n, float d,
-                                                 int32_t min_size, int32_t max_size) {
+                                                 int32_t min_size, int32_t max_size,
+                                                 uint64_t colgrid_cap) {
     float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY;
     float hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
     uint64_t cnt = 0;
@@ -198,6 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ parti
     }
     for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kBlock) (&P->hist[0][0])[i] = 0;
     if (threadIdx.x < kMaxPasses) P->ticket[threadIdx.x] = 0;
+    if (threadIdx.x < 8) P->counters[threadIdx.x] = 0;
     __syncthreads();
     if (threadIdx.x != 0) return;
 
@@ -241,6 +250,9 @@ __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ parti
     P->bx = bits_for(N3[0]);
     P->by = bits_for(N3[1]);
     P->bz = bits_for(N3[2]);
+    P->giant = -1;
+    P->nwork = 0;
+    P->dense_cols = ((double)N3[0] * (double)N3[1] <= (double)colgrid_cap) ? 1 : 0;
     const int B = P->bx + P->by + P->bz;
     const int kb = B + (((int64_t)c < n) ? 1 : 0);
     int ib = bits_for(n);
@@ -254,6 +266,13 @@ __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ parti
     P->key_shift = P->pair_mode ? 0 : ib;
     if (kb > 64) P->status = kStatusRange;
     P->npasses = P->status == kStatusOk ? (kb + kRadixBits - 1) / kRadixBits : 0;
+}
+
+// Cell key: cx, then cy, then cz.  The cells of one column (cx, cy) are
+// contiguous after sorting, and so are the columns of one row cx.
+__device__ __forceinline__ uint64_t make_key(uint64_t cx, uint64_t cy, uint64_t cz, int by,
+                                             int bz) {
+    return (((cx << by) | cy) << bz) | cz;
 }
 
 // ------------------------------------------------------------- 3. keys
@@ -288,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(const float *__restrict__ xyz,
             cx = cx < 0 ? 0 : (cx >= NX ? NX - 1 : cx);
             cy = cy < 0 ? 0 : (cy >= NY ? NY - 1 : cy);
             cz = cz < 0 ? 0 : (cz >= NZ ? NZ - 1 : cz);
-            key = ((uint64_t)cx << (by + bz)) | ((uint64_t)cy << bz) | (uint64_t)cz;
+            key = make_key((uint64_t)cx, (uint64_t)cy, (uint64_t)cz, by, bz);
         } else {
             key = invalid_key;
         }
@@ -336,6 +355,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(const uint64_t *__restrict
     if (pass >= P->npasses || P->status != kStatusOk) return;
     __shared__ uint32_t s_cnt[kBlock / 64][kRadix];
     __shared__ uint32_t s_base[kRadix];
+    __shared__ uint32_t s_local[kRadix];
+    __shared__ uint64_t s_buf[kTile];
+    __shared__ uint32_t s_vbuf[kTile];
     __shared__ uint32_t s_tmp[kBlock / 64];
     __shared__ uint32_t s_tile;
     __shared__ int s_fail;
@@ -417,25 +439,41 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(const uint64_t *__restrict
         }
         st_relaxed(mine, kLbInclusive | (excl + tcount));
     }
-    // global digit base: exclusive scan of the pass histogram
+    // global digit base (exclusive scan of the pass histogram plus the
+    // tiles before this one) and tile-local digit base
     uint32_t tot;
     const uint32_t hb = block_excl_scan(P->hist[pass][tid], s_tmp, tot);
     s_base[tid] = hb + (uint32_t)excl;
+    __syncthreads();
+    const uint32_t lb = block_excl_scan(tcount, s_tmp, tot);
+    s_local[tid] = lb;
     __syncthreads();
     if (s_fail) {
         if (tid == 0) atomicExch(&P->status, kStatusDevice);
         return;
     }
+    // stage the tile in LDS in digit order, then write each digit's run
+    // contiguously
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const int64_t e = base + k * 64 + lane;
         if (e < n) {
             const uint32_t dg = (uint32_t)(v[k] >> shift) & (kRadix - 1);
-            const uint64_t pos = (uint64_t)s_base[dg] + s_cnt[wave][dg] + rk[k];
-            if (pos < (uint64_t)n) {
-                dst[pos] = v[k];
-                if (pair) dstv[pos] = srcv[e];
-            }
+            const uint32_t lp = s_local[dg] + s_cnt[wave][dg] + rk[k];
+            s_buf[lp] = v[k];
+            if (pair) s_vbuf[lp] = srcv[e];
+        }
+    }
+    __syncthreads();
+    const int64_t rem = n - tile * kTile;
+    const int tile_n = rem < kTile ? (int)rem : kTile;
+    for (int j = tid; j < tile_n; j += kBlock) {
+        const uint64_t w = s_buf[j];
+        const uint32_t dg = (uint32_t)(w >> shift) & (kRadix - 1);
+        const uint64_t pos = (uint64_t)s_base[dg] + (uint32_t)(j - s_local[dg]);
+        if (pos < (uint64_t)n) {
+            dst[pos] = w;
+            if (pair) dstv[pos] = s_vbuf[j];
         }
     }
 }
@@ -457,6 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(const float *__restrict__ xyz
                                                    const uint64_t *__restrict__ s1,
                                                    const uint32_t *__restrict__ v0,
                                                    const uint32_t *__restrict__ v1,
+                                                   uint32_t *__restrict__ colbits,
                                                    Params *__restrict__ P,
                                                    float4 *__restrict__ spts,
                                                    uint32_t *__restrict__ sorig,
@@ -469,6 +508,12 @@ __global__ __launch_bounds__(kBlock) void k_gather(const float *__restrict__ xyz
     const bool pair = P->pair_mode != 0;
     const uint64_t mask = P->idx_mask;
     const int64_t base = (int64_t)blockIdx.x * kTile;
+    if (P->dense_cols) {  // clear the column occupancy bits
+        const uint64_t words = ((uint64_t)P->NX * (uint64_t)P->NY + 31) / 32;
+        for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < words;
+             i += (uint64_t)gridDim.x * kBlock)
+            colbits[i] = 0;
+    }
     uint32_t nc = 0, ncol = 0;
 #pragma unroll 4
     for (int k = 0; k < kItems; ++k) {
@@ -506,41 +551,40 @@ __global__ __launch_bounds__(kBlock) void k_gather(const float *__restrict__ xyz
 }
 
 // ------------------------------------------------------------- 6. tile scan
-// Exclusive scan of the per-tile cell / column counts (one block).
+// Exclusive scan of the per-tile counts of cell and column starts (one
+// block).
 __global__ __launch_bounds__(1024) void k_tile_scan(const uint32_t *__restrict__ tile_cnt,
                                                     uint32_t *__restrict__ tile_off,
                                                     int64_t ntiles, Params *__restrict__ P) {
     if (P->status != kStatusOk) return;
-    __shared__ uint32_t s_a[1024], s_b[1024];
+    __shared__ uint32_t s_v[2][1024];
     const int tid = threadIdx.x;
     const int64_t per = (ntiles + 1023) / 1024;
     const int64_t lo = tid * per, hi = lo + per < ntiles ? lo + per : ntiles;
-    uint32_t sa = 0, sb = 0;
-    for (int64_t t = lo; t < hi; ++t) {
-        sa += tile_cnt[2 * t];
-        sb += tile_cnt[2 * t + 1];
-    }
-    s_a[tid] = sa;
-    s_b[tid] = sb;
+    uint32_t own[2] = {0, 0};
+    for (int64_t t = lo; t < hi; ++t)
+        for (int c = 0; c < 2; ++c) own[c] += tile_cnt[2 * t + c];
+    for (int c = 0; c < 2; ++c) s_v[c][tid] = own[c];
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
-        uint32_t xa = tid >= o ? s_a[tid - o] : 0u, xb = tid >= o ? s_b[tid - o] : 0u;
+        uint32_t x[2];
+        for (int c = 0; c < 2; ++c) x[c] = tid >= o ? s_v[c][tid - o] : 0u;
         __syncthreads();
-        s_a[tid] += xa;
-        s_b[tid] += xb;
+        for (int c = 0; c < 2; ++c) s_v[c][tid] += x[c];
         __syncthreads();
     }
-    uint32_t ra = s_a[tid] - sa, rb = s_b[tid] - sb;
-    for (int64_t t = lo; t < hi; ++t) {
-        tile_off[2 * t] = ra;
-        tile_off[2 * t + 1] = rb;
-        ra += tile_cnt[2 * t];
-        rb += tile_cnt[2 * t + 1];
-    }
+    uint32_t run[2];
+    for (int c = 0; c < 2; ++c) run[c] = s_v[c][tid] - own[c];
+    for (int64_t t = lo; t < hi; ++t)
+        for (int c = 0; c < 2; ++c) {
+            tile_off[2 * t + c] = run[c];
+            run[c] += tile_cnt[2 * t + c];
+        }
     if (tid == 1023) {
-        P->M = s_a[1023];
-        P->Mcol = s_b[1023];
-        if ((int64_t)s_a[1023] > P->nvalid || s_b[1023] > s_a[1023]) {
+        const uint32_t M = s_v[0][1023], Mc = s_v[1][1023];
+        P->M = M;
+        P->Mcol = Mc;
+        if ((int64_t)M > P->nvalid || Mc > M) {
             P->status = kStatusDevice;  // inconsistent counts: stop before any table use
             P->M = 0;
             P->Mcol = 0;
@@ -549,16 +593,15 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const uint32_t *__restrict__
 }
 
 // ------------------------------------------------------------- 7. cells
-// Cell table (first sorted position and key of every occupied cell, and
-// its column) and column table (key (cx, cy) and first cell of every
-// occupied column), plus the per-cell union-find / size / id slots.
+// Cell table (first sorted position and key of every occupied cell) and
+// column table (key and first cell of every occupied column (cx, cy)), plus
+// the per-cell union-find / size / id slots.
 __global__ __launch_bounds__(kBlock) void k_cells(const uint64_t *__restrict__ s0,
                                                   const uint64_t *__restrict__ s1,
                                                   const Params *__restrict__ P,
                                                   const uint32_t *__restrict__ tile_off,
                                                   uint32_t *__restrict__ cell_start,
                                                   uint64_t *__restrict__ cell_key,
-                                                  uint32_t *__restrict__ cell_col,
                                                   uint64_t *__restrict__ col_key,
                                                   uint32_t *__restrict__ col_cell,
                                                   int32_t *__restrict__ cpar,
@@ -570,8 +613,7 @@ __global__ __launch_bounds__(kBlock) void k_cells(const uint64_t *__restrict__ s
     const int ks = P->key_shift, bz = P->bz;
     const int64_t base = (int64_t)blockIdx.x * kTile;
     const int wave = threadIdx.x >> 6, lane = __lane_id();
-    __shared__ uint32_t s_tot[kItems][kBlock / 64];
-    __shared__ uint32_t s_ctot[kItems][kBlock / 64];
+    __shared__ uint32_t s_tot[2][kItems][kBlock / 64];
     uint32_t flags = 0, cflags = 0;
     for (int k = 0; k < kItems; ++k) {
         const int64_t e = base + k * kBlock + threadIdx.x;
@@ -582,20 +624,18 @@ __global__ __launch_bounds__(kBlock) void k_cells(const uint64_t *__restrict__ s
         cflags |= (uint32_t)cf << k;
         const uint64_t m = __ballot(f), mc = __ballot(cf);
         if (lane == 0) {
-            s_tot[k][wave] = (uint32_t)__popcll(m);
-            s_ctot[k][wave] = (uint32_t)__popcll(mc);
+            s_tot[0][k][wave] = (uint32_t)__popcll(m);
+            s_tot[1][k][wave] = (uint32_t)__popcll(mc);
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t run = 0, crun = 0;
+    if (threadIdx.x < 2) {
+        uint32_t run = 0;
         for (int k = 0; k < kItems; ++k)
             for (int w = 0; w < kBlock / 64; ++w) {
-                const uint32_t t = s_tot[k][w], c = s_ctot[k][w];
-                s_tot[k][w] = run;
-                s_ctot[k][w] = crun;
+                const uint32_t t = s_tot[threadIdx.x][k][w];
+                s_tot[threadIdx.x][k][w] = run;
                 run += t;
-                crun += c;
             }
     }
     __syncthreads();
@@ -606,13 +646,12 @@ __global__ __launch_bounds__(kBlock) void k_cells(const uint64_t *__restrict__ s
         const uint64_t m = __ballot(f), mc = __ballot(cf);
         if (f) {
             const int64_t e = base + k * kBlock + threadIdx.x;
-            const uint32_t cid = c0 + s_tot[k][wave] + (uint32_t)__popcll(m & lt);
-            const uint32_t colx = q0 + s_ctot[k][wave] + (uint32_t)__popcll(mc & lt);
+            const uint32_t cid = c0 + s_tot[0][k][wave] + (uint32_t)__popcll(m & lt);
+            const uint32_t colx = q0 + s_tot[1][k][wave] + (uint32_t)__popcll(mc & lt);
             if ((int64_t)cid >= nvalid) continue;
             const uint64_t key = srt[e] >> ks;
             cell_start[cid] = (uint32_t)e;
             cell_key[cid] = key;
-            cell_col[cid] = cf ? colx : colx - 1;
             cpar[cid] = (int32_t)cid;
             csize[cid] = 0;
             ccanon[cid] = 0xFFFFFFFFu;
@@ -624,48 +663,90 @@ __global__ __launch_bounds__(kBlock) void k_cells(const uint64_t *__restrict__ s
     }
 }
 
-// ------------------------------------------------------------- 8. column rows
-// For every column (cx, cy), the first column of rows cx+1 and cx+2 whose
-// cy' >= cy - 2 (columns are sorted by (cx, cy), so the columns of the
-// stencil in one row are consecutive from there).
-__global__ __launch_bounds__(kBlock) void k_colrows(const uint64_t *__restrict__ col_key,
+// Column coordinates <-> column key (see make_key).
+struct Grid {
+    int by, bz;
+    int64_t NX, NY;
+    uint64_t zmask, ymask;
+
+    __device__ __forceinline__ uint64_t col_key(uint64_t cx, uint64_t cy) const {
+        return (cx << by) | cy;
+    }
+    __device__ __forceinline__ void col_xy(uint64_t ck, int64_t &cx, int64_t &cy) const {
+        cx = (int64_t)(ck >> by);
+        cy = (int64_t)(ck & ymask);
+    }
+};
+
+__device__ __forceinline__ Grid grid_of(const Params *P) {
+    Grid g;
+    g.by = P->by;
+    g.bz = P->bz;
+    g.NX = P->NX;
+    g.NY = P->NY;
+    g.zmask = (1ull << P->bz) - 1;
+    g.ymask = (1ull << P->by) - 1;
+    return g;
+}
+
+// Dense column index: colgrid[cx * NY + cy] = first cell of column (cx, cy),
+// valid where the occupancy bit is set (bits are cleared every call, the
+// index itself is not).  Also writes the end markers of the cell and column
+// tables.
+__global__ __launch_bounds__(kBlock) void k_colgrid(const uint64_t *__restrict__ col_key,
                                                     uint32_t *__restrict__ col_cell,
                                                     uint32_t *__restrict__ cell_start,
-                                                    uint32_t *__restrict__ row_start,
+                                                    uint32_t *__restrict__ colgrid,
+                                                    uint32_t *__restrict__ colbits,
                                                     const Params *__restrict__ P) {
     if (P->status != kStatusOk) return;
     const int64_t Mcol = P->Mcol;
-    const int by = P->by;
-    const uint64_t ymask = (1ull << by) - 1;
-    const int64_t NX = P->NX;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         col_cell[Mcol] = (uint32_t)P->M;
         cell_start[P->M] = (uint32_t)P->nvalid;
     }
+    if (!P->dense_cols) return;
+    const Grid g = grid_of(P);
     for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < Mcol;
          c += (int64_t)gridDim.x * kBlock) {
-        const uint64_t ck = col_key[c];
-        const uint64_t cx = ck >> by, cy = ck & ymask;
-        for (int dx = 1; dx <= 2; ++dx) {
-            uint32_t rs = (uint32_t)Mcol;
-            if ((int64_t)(cx + dx) < NX) {
-                const uint64_t target = ((cx + dx) << by) | (cy >= 2 ? cy - 2 : 0);
-                uint32_t lo = (uint32_t)c + 1, hi = (uint32_t)Mcol;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (col_key[mid] < target) lo = mid + 1;
-                    else hi = mid;
-                }
-                rs = lo;
-            }
-            row_start[2 * c + dx - 1] = rs;
-        }
+        int64_t cx, cy;
+        g.col_xy(col_key[c], cx, cy);
+        const uint64_t idx = (uint64_t)(cx * g.NY + cy);
+        colgrid[idx] = col_cell[c];
+        atomicOr(&colbits[idx >> 5], 1u << (idx & 31));
     }
 }
 
-// ------------------------------------------------------------- 9. hooking
-// Union-find over cells; parent[x] <= x always, roots are the smallest cell
-// of their component.
+// First cell of column (cx, cy), or false when the column is empty or off
+// the grid.
+__device__ __forceinline__ bool find_column(const Grid &g, int64_t cx, int64_t cy, int dense,
+                                            const uint32_t *__restrict__ colgrid,
+                                            const uint32_t *__restrict__ colbits,
+                                            const uint64_t *__restrict__ col_key,
+                                            const uint32_t *__restrict__ col_cell, int64_t Mcol,
+                                            uint32_t &first) {
+    if (cx < 0 || cx >= g.NX || cy < 0 || cy >= g.NY) return false;
+    if (dense) {
+        const uint64_t idx = (uint64_t)(cx * g.NY + cy);
+        if (!((colbits[idx >> 5] >> (idx & 31)) & 1u)) return false;
+        first = colgrid[idx];
+        return true;
+    }
+    const uint64_t want = g.col_key((uint64_t)cx, (uint64_t)cy);
+    int64_t lo = 0, hi = Mcol;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (col_key[mid] < want) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo >= Mcol || col_key[lo] != want) return false;
+    first = col_cell[lo];
+    return true;
+}
+
+// ------------------------------------------------------------- 8. hooking
+// Union-find over cells; parent[x] <= x always, so a root is the smallest
+// cell of its component.
 __device__ __forceinline__ int32_t uf_find(int32_t *par, int32_t x) {
     int32_t p = ld_relaxed(par + x);
     while (p != x) {
@@ -686,117 +767,279 @@ __device__ __forceinline__ int32_t uf_find_ro(const int32_t *par, int32_t x) {
     return x;
 }
 
-__device__ __forceinline__ void uf_link(int32_t *par, int32_t a, int32_t b) {
+// Joins the components of a and b; returns the root of the union (at the
+// time of the join).
+__device__ __forceinline__ int32_t uf_link(int32_t *par, int32_t a, int32_t b) {
     while (true) {
         a = uf_find(par, a);
         b = uf_find(par, b);
-        if (a == b) return;
+        if (a == b) return a;
         if (a < b) {
             const int32_t t = a;
             a = b;
             b = t;
         }
         // hook the larger root a under the smaller root b
-        if (atomicCAS(par + a, a, b) == a) return;
+        if (atomicCAS(par + a, a, b) == a) return b;
     }
 }
 
-// Tests the cell pair (A, B) point pair by point pair until the first
-// joined pair; joins their components when one is found.  Skips pairs that
-// already share a root.
-__device__ __forceinline__ void hook_pair(int32_t A, int32_t B, uint32_t sA, uint32_t eA,
-                                          const float4 *__restrict__ spts,
-                                          const uint32_t *__restrict__ cell_start,
-                                          int32_t *cpar, float d2) {
-    const int32_t ra = uf_find(cpar, A);
-    const int32_t rb = uf_find(cpar, B);
-    if (ra == rb) return;
-    const uint32_t sB = cell_start[B], eB = cell_start[B + 1];
+// Is there a joined pair between the points [sA, eA) and [sB, eB)?  Stops at
+// the first one.
+__device__ __forceinline__ bool any_joined(const float4 *__restrict__ spts, uint32_t sA,
+                                           uint32_t eA, uint32_t sB, uint32_t eB, float d2) {
     for (uint32_t a = sA; a < eA; ++a) {
         const float4 pa = spts[a];
-        for (uint32_t b = sB; b < eB; ++b) {
-            if (joined(pa.x, pa.y, pa.z, spts[b], d2)) {
-                uf_link(cpar, ra, rb);
-                return;
-            }
+        for (uint32_t b = sB; b < eB; ++b)
+            if (joined(pa.x, pa.y, pa.z, spts[b], d2)) return true;
+    }
+    return false;
+}
+
+// Runs: cell B = A + 1 (the next cell in key order) is often A's neighbour
+// one step up in z, or one step along y in the next column.  Such a pair is
+// tested; each cell that is not joined to its predecessor this way starts a
+// run.  Every cell of a run is connected to the run's first cell, which
+// becomes its parent: a valid union-find state (parent <= cell, same
+// component) reached without atomics.
+__device__ __forceinline__ bool next_is_near(const Grid &g, uint64_t ka, uint64_t kb) {
+    const uint64_t ca = ka >> g.bz, cb = kb >> g.bz;
+    const int64_t za = (int64_t)(ka & g.zmask), zb = (int64_t)(kb & g.zmask);
+    if (ca == cb) return zb == za + 1;
+    int64_t xa, ya, xb, yb;
+    g.col_xy(ca, xa, ya);
+    g.col_xy(cb, xb, yb);
+    return xb == xa && yb == ya + 1 && zb - za >= -1 && zb - za <= 1;
+}
+
+// Pass 1: run-start flags per cell, and the last run start of every block
+// of kTile cells.
+__global__ __launch_bounds__(kBlock) void k_runs1(const float4 *__restrict__ spts,
+                                                  const uint32_t *__restrict__ cell_start,
+                                                  const uint64_t *__restrict__ cell_key,
+                                                  uint8_t *__restrict__ heads,
+                                                  int32_t *__restrict__ blkhead,
+                                                  const Params *__restrict__ P) {
+    if (P->status != kStatusOk) return;
+    const int64_t M = P->M;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    if (base >= M) return;
+    const float d2 = P->d2;
+    const Grid g = grid_of(P);
+    int32_t last = -1;
+    for (int k = 0; k < kItems; ++k) {
+        const int64_t A = base + k * kBlock + threadIdx.x;
+        if (A >= M) break;
+        bool head = true;
+        if (A > 0) {
+            const uint64_t kp = cell_key[A - 1], ka = cell_key[A];
+            if (next_is_near(g, kp, ka))
+                head = !any_joined(spts, cell_start[A - 1], cell_start[A], cell_start[A],
+                                   cell_start[A + 1], d2);
         }
+        heads[A] = head ? 1 : 0;
+        if (head) last = (int32_t)A;
+    }
+    // block max of the last run start
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int32_t w = __shfl_xor(last, o);
+        last = w > last ? w : last;
+    }
+    __shared__ int32_t s_w[kBlock / 64];
+    if (__lane_id() == 0) s_w[threadIdx.x >> 6] = last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t m = -1;
+        for (int w = 0; w < kBlock / 64; ++w) m = s_w[w] > m ? s_w[w] : m;
+        blkhead[blockIdx.x] = m;
     }
 }
 
-// One shell of the forward half of the 5x5x5 stencil around every cell.
-// ROUND 0 (near): offsets with max(|dx|,|dy|,|dz|) = 1.
-// ROUND 1 (far):  offsets with max(|dx|,|dy|,|dz|) = 2.
-// Forward: dx > 0, or dx == 0 and dy > 0, or dx == dy == 0 and dz > 0.
-template <int ROUND>
-__global__ __launch_bounds__(kBlock) void k_hook(const float4 *__restrict__ spts,
-                                                 const uint32_t *__restrict__ cell_start,
-                                                 const uint64_t *__restrict__ cell_key,
-                                                 const uint32_t *__restrict__ cell_col,
-                                                 const uint64_t *__restrict__ col_key,
-                                                 const uint32_t *__restrict__ col_cell,
-                                                 const uint32_t *__restrict__ row_start,
-                                                 int32_t *cpar, const Params *__restrict__ P) {
+// Pass 2: parent of every cell = the last run start at or before it.
+__global__ __launch_bounds__(kBlock) void k_runs2(const uint8_t *__restrict__ heads,
+                                                  const int32_t *__restrict__ blkhead,
+                                                  int32_t *__restrict__ cpar,
+                                                  const Params *__restrict__ P) {
+    if (P->status != kStatusOk) return;
+    const int64_t M = P->M;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    if (base >= M) return;
+    const int wave = threadIdx.x >> 6, lane = __lane_id();
+    __shared__ int32_t s_last[kItems][kBlock / 64];
+    __shared__ int32_t s_carry[kItems][kBlock / 64];
+    uint32_t hf = 0;
+    for (int k = 0; k < kItems; ++k) {
+        const int64_t A = base + k * kBlock + threadIdx.x;
+        const bool h = A < M && heads[A];
+        hf |= (uint32_t)h << k;
+        const uint64_t m = __ballot(h);
+        if (lane == 0) s_last[k][wave] = m ? (int32_t)(base + k * kBlock + wave * 64 + 63 - __clzll(m)) : -1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // run start before this block: nearest earlier block that has one
+        int32_t carry = 0;
+        for (int64_t b = (int64_t)blockIdx.x - 1; b >= 0; --b) {
+            const int32_t h = blkhead[b];
+            if (h >= 0) {
+                carry = h;
+                break;
+            }
+        }
+        for (int k = 0; k < kItems; ++k)
+            for (int w = 0; w < kBlock / 64; ++w) {
+                s_carry[k][w] = carry;
+                if (s_last[k][w] >= 0) carry = s_last[k][w];
+            }
+    }
+    __syncthreads();
+    for (int k = 0; k < kItems; ++k) {
+        const int64_t A = base + k * kBlock + threadIdx.x;
+        const uint64_t m = __ballot((hf >> k) & 1u);
+        if (A >= M) continue;
+        const uint64_t upto = m & (lane == 63 ? ~0ull : ((2ull << lane) - 1));
+        const int32_t p = upto ? (int32_t)(base + k * kBlock + wave * 64 + 63 - __clzll(upto))
+                               : s_carry[k][wave];
+        cpar[A] = p;
+    }
+}
+
+// Forward half of the 5x5x5 stencil by column offset (dx, dy): the near
+// shell (max(|dx|,|dy|,|dz|) == 1) uses the first four columns with
+// |dz| <= 1; the own column contributes dz = +1.
+struct StencilCol {
+    int8_t dx, dy;
+};
+__constant__ StencilCol kNearCols[4] = {{0, 1}, {1, -1}, {1, 0}, {1, 1}};
+
+// Near shell over every cell: a cell pair is skipped when both cells
+// already share a root; otherwise point pairs are tested until the first
+// joined one, which joins the two components.
+//
+// The kernel is latency bound, so the loads of one cell are issued in a
+// few independent rounds rather than as one long dependent chain: (1) the
+// cell's own key, points and parent; (2) occupancy bit and index entry of
+// the four neighbour columns; (3) the first kNearK cells of each of those
+// columns; (4) the parents of every candidate cell.  Only then are the
+// candidates whose component differs tested one by one.  Columns with more
+// than kNearK cells in reach fall back to a plain scan.
+constexpr int kNearK = 3;
+
+__global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__ spts,
+                                                      const uint32_t *__restrict__ cell_start,
+                                                      const uint64_t *__restrict__ cell_key,
+                                                      const uint64_t *__restrict__ col_key,
+                                                      const uint32_t *__restrict__ col_cell,
+                                                      const uint32_t *__restrict__ colgrid,
+                                                      const uint32_t *__restrict__ colbits,
+                                                      int32_t *cpar, const Params *__restrict__ P) {
     if (P->status != kStatusOk) return;
     const int64_t M = P->M, Mcol = P->Mcol;
+    const int dense = P->dense_cols;
     const float d2 = P->d2;
-    const int by = P->by, bz = P->bz;
-    const uint64_t zmask = (1ull << bz) - 1, ymask = (1ull << by) - 1;
-    constexpr int zr = ROUND == 0 ? 1 : 2;
+    const Grid g = grid_of(P);
+    constexpr int kC = 4;
+    constexpr int kCand = kC * kNearK + 1;
     for (int64_t Ai = (int64_t)blockIdx.x * kBlock + threadIdx.x; Ai < M;
          Ai += (int64_t)gridDim.x * kBlock) {
         const int32_t A = (int32_t)Ai;
+        // round 1
         const uint64_t key = cell_key[A];
-        const int64_t cz = (int64_t)(key & zmask);
-        const uint64_t ck = key >> bz;
-        const int64_t cx = (int64_t)(ck >> by), cy = (int64_t)(ck & ymask);
-        const uint32_t col = cell_col[A];
+        const uint64_t kup = A + 1 < M ? cell_key[A + 1] : ~0ull;
         const uint32_t sA = cell_start[A], eA = cell_start[A + 1];
-
-        auto scan_column = [&](uint32_t c2, int64_t dx, int64_t dy) {
-            const bool near_col = dx <= 1 && dy <= 1 && dy >= -1;
-            const uint32_t b0 = col_cell[c2], b1 = col_cell[c2 + 1];
-            uint32_t lo = b0, hi = b1;
-            if (b1 - b0 > 8) {  // first cell with cz' >= cz - zr
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if ((int64_t)(cell_key[mid] & zmask) < cz - zr) lo = mid + 1;
-                    else hi = mid;
+        const int32_t p0 = ld_relaxed(cpar + A);
+        const uint64_t ck = key >> g.bz;
+        const int64_t cz = (int64_t)(key & g.zmask);
+        int64_t cx, cy;
+        g.col_xy(ck, cx, cy);
+        // round 2: neighbour columns
+        bool has[kC];
+        uint32_t fc[kC];
+        uint64_t want[kC];
+#pragma unroll
+        for (int o = 0; o < kC; ++o) {
+            const StencilCol sc = kNearCols[o];
+            const int64_t nx = cx + sc.dx, ny = cy + sc.dy;
+            want[o] = g.col_key((uint64_t)nx, (uint64_t)ny);
+            if (dense) {
+                const bool in = nx < g.NX && ny >= 0 && ny < g.NY;
+                const uint64_t idx = in ? (uint64_t)(nx * g.NY + ny) : 0;
+                const uint32_t wd = in ? colbits[idx >> 5] : 0u;
+                const uint32_t f = in ? colgrid[idx] : 0u;
+                has[o] = (wd >> (idx & 31)) & 1u;
+                fc[o] = f;
+            } else {
+                has[o] = find_column(g, nx, ny, 0, colgrid, colbits, col_key, col_cell, Mcol, fc[o]);
+            }
+        }
+        // round 3: first cells of each column
+        uint64_t kk[kC][kNearK];
+#pragma unroll
+        for (int o = 0; o < kC; ++o)
+#pragma unroll
+            for (int j = 0; j < kNearK; ++j) {
+                const int64_t B = (int64_t)fc[o] + j;
+                kk[o][j] = (has[o] && B < M) ? cell_key[B] : ~0ull;
+            }
+        const int32_t q0 = ld_relaxed(cpar + p0);
+        // candidates (existence is tracked explicitly: a key sentinel could
+        // equal the wrapped key of a column off the grid)
+        uint32_t cm = 0, ovf = 0;
+        if (A + 1 < M && (kup >> g.bz) == ck && (int64_t)(kup & g.zmask) == cz + 1)
+            cm |= 1u << (kCand - 1);
+#pragma unroll
+        for (int o = 0; o < kC; ++o) {
+#pragma unroll
+            for (int j = 0; j < kNearK; ++j) {
+                const bool loaded = has[o] && (int64_t)fc[o] + j < M;
+                const bool inc = loaded && (kk[o][j] >> g.bz) == want[o];
+                const int64_t dz = (int64_t)(kk[o][j] & g.zmask) - cz;
+                if (inc && dz >= -1 && dz <= 1) cm |= 1u << (o * kNearK + j);
+                if (j == kNearK - 1 && inc && dz < 1) ovf |= 1u << o;
+            }
+        }
+        // round 4: parents of the candidates
+        int32_t rb[kCand];
+#pragma unroll
+        for (int i = 0; i < kCand; ++i) {
+            const uint32_t B = i == kCand - 1 ? (uint32_t)A + 1 : fc[i / kNearK] + (uint32_t)(i % kNearK);
+            rb[i] = ((cm >> i) & 1u) ? ld_relaxed(cpar + B) : -1;
+        }
+        int32_t ra = (q0 == p0) ? p0 : uf_find(cpar, q0);
+        FEC_COUNT(P, 0, __popc(cm));
+#pragma unroll
+        for (int i = 0; i < kCand; ++i) {
+            if (!((cm >> i) & 1u)) continue;
+            int32_t r = rb[i];
+            if (r == ra || r == p0) continue;
+            r = uf_find(cpar, r);
+            if (r == ra) continue;
+            const uint32_t B = i == kCand - 1 ? (uint32_t)A + 1 : fc[i / kNearK] + (uint32_t)(i % kNearK);
+            FEC_COUNT(P, 1, 1);
+            const uint32_t sB = cell_start[B], eB = cell_start[B + 1];
+            FEC_COUNT(P, 3, (eA - sA) * (eB - sB));
+            if (any_joined(spts, sA, eA, sB, eB, d2)) {
+                FEC_COUNT(P, 2, 1);
+                ra = uf_link(cpar, ra, r);
+            }
+        }
+        FEC_COUNT(P, 4, __popc(ovf));
+        // columns with more cells in reach than were loaded
+        if (ovf) {
+            for (int o = 0; o < kC; ++o) {
+                if (!((ovf >> o) & 1u)) continue;
+                for (uint32_t B = fc[o] + kNearK; (int64_t)B < M; ++B) {
+                    const uint64_t kb = cell_key[B];
+                    if ((kb >> g.bz) != want[o]) break;
+                    const int64_t dz = (int64_t)(kb & g.zmask) - cz;
+                    if (dz > 1) break;
+                    if (dz < -1) continue;
+                    const int32_t r = uf_find(cpar, (int32_t)B);
+                    if (r == ra) continue;
+                    if (any_joined(spts, sA, eA, cell_start[B], cell_start[B + 1], d2))
+                        ra = uf_link(cpar, ra, r);
                 }
-            }
-            for (uint32_t B = lo; B < b1; ++B) {
-                const int64_t dz = (int64_t)(cell_key[B] & zmask) - cz;
-                if (dz < -zr) continue;
-                if (dz > zr) break;
-                if (ROUND == 1 && near_col && dz >= -1 && dz <= 1) continue;
-                hook_pair(A, (int32_t)B, sA, eA, spts, cell_start, cpar, d2);
-            }
-        };
-
-        // own column, cells above: dz = +zr
-        for (int32_t B = A + 1; B < M && B <= A + 2; ++B) {
-            const uint64_t kb = cell_key[B];
-            if ((kb >> bz) != ck) break;
-            const int64_t dz = (int64_t)(kb & zmask) - cz;
-            if (dz > zr) break;
-            if (dz == zr) hook_pair(A, B, sA, eA, spts, cell_start, cpar, d2);
-        }
-        // row dx = 0: columns cy+1 .. cy+zr follow this column directly
-        for (uint32_t c2 = col + 1; c2 <= col + zr && (int64_t)c2 < Mcol; ++c2) {
-            const uint64_t k2 = col_key[c2];
-            if ((int64_t)(k2 >> by) != cx) break;
-            const int64_t dy = (int64_t)(k2 & ymask) - cy;
-            if (dy > zr) break;
-            scan_column(c2, 0, dy);
-        }
-        // rows dx = 1 (and 2 in the far shell)
-        for (int dx = 1; dx <= zr; ++dx) {
-            for (uint32_t c2 = row_start[2 * col + dx - 1]; (int64_t)c2 < Mcol; ++c2) {
-                const uint64_t k2 = col_key[c2];
-                if ((int64_t)(k2 >> by) != cx + dx) break;
-                const int64_t dy = (int64_t)(k2 & ymask) - cy;
-                if (dy > zr) break;
-                if (dy < -zr) continue;
-                scan_column(c2, dx, dy);
             }
         }
     }
@@ -814,7 +1057,176 @@ __global__ __launch_bounds__(kBlock) void k_compress(int32_t *cpar, const Params
     }
 }
 
-// ------------------------------------------------------------- 10. finalize
+// The most frequent root among up to 4096 evenly spaced cells.  One block.
+constexpr int kGiantSample = 4096;
+constexpr int kGiantSlots = 8192;
+
+__global__ __launch_bounds__(1024) void k_giant(const int32_t *__restrict__ cpar,
+                                                Params *__restrict__ P) {
+    if (P->status != kStatusOk) return;
+    __shared__ int32_t t_key[kGiantSlots];
+    __shared__ uint32_t t_cnt[kGiantSlots];
+    __shared__ uint64_t s_best[1024 / 64];
+    const int64_t M = P->M;
+    for (int i = threadIdx.x; i < kGiantSlots; i += 1024) {
+        t_key[i] = -1;
+        t_cnt[i] = 0;
+    }
+    __syncthreads();
+    const int64_t S = M < kGiantSample ? M : kGiantSample;
+    for (int64_t i = threadIdx.x; i < S; i += 1024) {
+        const int32_t r = cpar[i * M / S];
+        uint32_t h = ((uint32_t)r * 2654435761u) >> (32 - 13);
+        for (int probe = 0; probe < kGiantSlots; ++probe) {
+            const int32_t prev = atomicCAS(&t_key[h], -1, r);
+            if (prev == -1 || prev == r) {
+                atomicAdd(&t_cnt[h], 1u);
+                break;
+            }
+            h = (h + 1) & (kGiantSlots - 1);
+        }
+    }
+    __syncthreads();
+    // best = max count, then smallest root: pack (count, ~root) into 64 bits
+    uint64_t best = 0;
+    for (int i = threadIdx.x; i < kGiantSlots; i += 1024) {
+        const int32_t r = t_key[i];
+        if (r >= 0) {
+            const uint64_t v = ((uint64_t)t_cnt[i] << 32) | (uint64_t)(0x7FFFFFFFu - (uint32_t)r);
+            best = v > best ? v : best;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t w = __shfl_xor(best, o);
+        best = w > best ? w : best;
+    }
+    if (__lane_id() == 0) s_best[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t b = 0;
+        for (int w = 0; w < 1024 / 64; ++w) b = s_best[w] > b ? s_best[w] : b;
+        P->giant = b ? (int32_t)(0x7FFFFFFFu - (uint32_t)(b & 0xFFFFFFFFu)) : -1;
+        P->nwork = 0;
+    }
+}
+
+// Bitmap of the cells in the giant component (after the near shell) and
+// the list of the others (the far-shell work list); the list append is
+// aggregated per block.
+__global__ __launch_bounds__(kBlock) void k_nongiant(const int32_t *__restrict__ cpar,
+                                                     uint64_t *__restrict__ gbits,
+                                                     uint32_t *__restrict__ work,
+                                                     Params *__restrict__ P) {
+    if (P->status != kStatusOk) return;
+    __shared__ uint32_t s_wcnt[kBlock / 64];
+    __shared__ uint32_t s_base;
+    const int64_t M = P->M;
+    const int32_t giant = P->giant;
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    for (int64_t b0 = (int64_t)blockIdx.x * kBlock; b0 < M; b0 += (int64_t)gridDim.x * kBlock) {
+        const int64_t A = b0 + threadIdx.x;
+        const bool valid = A < M;
+        const bool gi = valid && cpar[A] == giant;
+        const uint64_t gm = __ballot(gi);
+        if (lane == 0 && valid) gbits[A >> 6] = gm;  // A is 64-aligned on lane 0
+        const bool w = valid && !gi;
+        const uint64_t wm = __ballot(w);
+        if (lane == 0) s_wcnt[wave] = (uint32_t)__popcll(wm);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+            for (int i = 0; i < kBlock / 64; ++i) {
+                const uint32_t c = s_wcnt[i];
+                s_wcnt[i] = tot;
+                tot += c;
+            }
+            s_base = tot ? atomicAdd(&P->nwork, tot) : 0u;
+        }
+        __syncthreads();
+        if (w) work[s_base + s_wcnt[wave] + (uint32_t)__popcll(wm & lanemask_lt())] = (uint32_t)A;
+        __syncthreads();
+    }
+}
+
+// Far shell (max(|dx|,|dy|,|dz|) == 2) around every cell outside the giant
+// component.  A cell pair is handled here when its first cell is outside
+// the giant component and either the pair is "forward" (dx > 0, or dx == 0
+// and dy > 0, or dx == dy == 0 and dz > 0) or the second cell is inside it.
+// So every far pair with at least one cell outside the giant component is
+// handled; pairs with both cells inside are already joined.
+__device__ __forceinline__ bool is_giant(const uint64_t *__restrict__ gbits, uint32_t B) {
+    return (gbits[B >> 6] >> (B & 63)) & 1ull;
+}
+
+__global__ __launch_bounds__(kBlock) void k_hook_far(const float4 *__restrict__ spts,
+                                                      const uint32_t *__restrict__ cell_start,
+                                                      const uint64_t *__restrict__ cell_key,
+                                                      const uint64_t *__restrict__ col_key,
+                                                      const uint32_t *__restrict__ col_cell,
+                                                      const uint32_t *__restrict__ colgrid,
+                                                      const uint32_t *__restrict__ colbits,
+                                                      const uint64_t *__restrict__ gbits,
+                                                      const uint32_t *__restrict__ work,
+                                                      int32_t *cpar, const Params *__restrict__ P) {
+    if (P->status != kStatusOk) return;
+    const int64_t M = P->M, Mcol = P->Mcol;
+    const uint32_t nwork = P->nwork;
+    const int dense = P->dense_cols;
+    const float d2 = P->d2;
+    const Grid g = grid_of(P);
+    for (uint32_t wi = blockIdx.x * kBlock + threadIdx.x; wi < nwork; wi += gridDim.x * kBlock) {
+        const int32_t A = (int32_t)work[wi];
+        const uint64_t key = cell_key[A];
+        const uint64_t ck = key >> g.bz;
+        const int64_t cz = (int64_t)(key & g.zmask);
+        int64_t cx, cy;
+        g.col_xy(ck, cx, cy);
+        const uint32_t sA = cell_start[A], eA = cell_start[A + 1];
+        int32_t ra = uf_find(cpar, A);
+        auto pair = [&](uint32_t B) {
+            const int32_t rb = uf_find(cpar, (int32_t)B);
+            if (rb == ra) return;
+            if (any_joined(spts, sA, eA, cell_start[B], cell_start[B + 1], d2))
+                ra = uf_link(cpar, ra, rb);
+        };
+        // own column: the cells two steps down (if giant) and up
+        for (int32_t B = A - 1; B >= 0 && B >= A - 2; --B) {
+            const uint64_t kb = cell_key[B];
+            const int64_t dz = cz - (int64_t)(kb & g.zmask);
+            if ((kb >> g.bz) != ck || dz > 2) break;
+            if (dz == 2 && is_giant(gbits, (uint32_t)B)) pair((uint32_t)B);
+        }
+        for (int32_t B = A + 1; B < M && B <= A + 2; ++B) {
+            const uint64_t kb = cell_key[B];
+            const int64_t dz = (int64_t)(kb & g.zmask) - cz;
+            if ((kb >> g.bz) != ck || dz > 2) break;
+            if (dz == 2) pair((uint32_t)B);
+        }
+        for (int dx = -2; dx <= 2; ++dx)
+            for (int dy = -2; dy <= 2; ++dy) {
+                if (dx == 0 && dy == 0) continue;
+                const bool fwd = dx > 0 || (dx == 0 && dy > 0);
+                const bool near_col = dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1;
+                uint32_t f;
+                if (!find_column(g, cx + dx, cy + dy, dense, colgrid, colbits, col_key, col_cell,
+                                 Mcol, f))
+                    continue;
+                const uint64_t want = g.col_key((uint64_t)(cx + dx), (uint64_t)(cy + dy));
+                for (uint32_t B = f; (int64_t)B < M; ++B) {
+                    const uint64_t kb = cell_key[B];
+                    if ((kb >> g.bz) != want) break;
+                    const int64_t dz = (int64_t)(kb & g.zmask) - cz;
+                    if (dz > 2) break;
+                    if (dz < -2) continue;
+                    if (near_col && dz >= -1 && dz <= 1) continue;  // near shell: done
+                    if (fwd || is_giant(gbits, B)) pair(B);
+                }
+            }
+    }
+}
+
+// ------------------------------------------------------------- 9. finalize
 // Cluster sizes and smallest original index per root.  Each block takes a
 // contiguous run of cells and adds them into a block-local hash table of
 // roots in LDS (one root of a giant component takes most cells, and global
@@ -958,9 +1370,9 @@ __global__ void k_finish(const Params *__restrict__ P, int32_t *__restrict__ k_o
 
 const char *stage_name(int s) {
     static const char *names[kNumStages] = {
-        "bbox",      "plan",       "keys",        "sort_pass",    "gather",
-        "tile_scan", "cells",      "column_rows", "hook_near",    "compress_1",
-        "hook_far",  "compress_2", "final_cells", "final_labels", "finish"};
+        "bbox",      "plan",       "keys",      "sort_pass",  "gather",      "tile_scan",
+        "cells",     "colgrid",    "runs",      "hook_near",  "compress_1",  "giant",
+        "work_list", "hook_far",   "compress_2", "final_cells", "final_labels", "finish"};
     return (s >= 0 && s < kNumStages) ? names[s] : "";
 }
 
@@ -985,10 +1397,14 @@ hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_siz
     int32_t *cpar = reinterpret_cast<int32_t *>(w + L.cpar);
     uint32_t *csize = reinterpret_cast<uint32_t *>(w + L.csize);
     uint32_t *ccanon = reinterpret_cast<uint32_t *>(w + L.ccanon);
-    uint32_t *cell_col = reinterpret_cast<uint32_t *>(w + L.cell_col);
     uint64_t *col_key = reinterpret_cast<uint64_t *>(w + L.col_key);
     uint32_t *col_cell = reinterpret_cast<uint32_t *>(w + L.col_cell);
-    uint32_t *row_start = reinterpret_cast<uint32_t *>(w + L.row_start);
+    uint32_t *colgrid = reinterpret_cast<uint32_t *>(w + L.colgrid);
+    uint32_t *colbits = reinterpret_cast<uint32_t *>(w + L.colbits);
+    uint8_t *heads = reinterpret_cast<uint8_t *>(w + L.heads);
+    int32_t *blkhead = reinterpret_cast<int32_t *>(w + L.blkhead);
+    uint64_t *gbits = reinterpret_cast<uint64_t *>(w + L.gbits);
+    uint32_t *work = reinterpret_cast<uint32_t *>(w + L.work);
 
     const int64_t ntiles = L.ntiles;
     int nb_bbox = (int)((n + kBlock * 4 - 1) / (kBlock * 4));
@@ -1011,7 +1427,7 @@ hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_siz
 
     FEC_LAUNCH(kStBbox, k_bbox<<<nb_bbox, kBlock, 0, st>>>(xyz, n, partials));
     FEC_LAUNCH(kStPlan, k_plan<<<1, kBlock, 0, st>>>(partials, nb_bbox, P, n, d, min_size,
-                                                      max_size));
+                                                      max_size, L.colgrid_cap));
     FEC_LAUNCH(kStKeys, k_keys<<<nb_stream, kBlock, 0, st>>>(xyz, P, keys0, vals0, lb0,
                                                               ntiles * kRadix));
     for (int pass = 0; pass < max_passes; ++pass) {
@@ -1025,20 +1441,26 @@ hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_siz
                                 src, dst, srcv, dstv, P, cur, nxt, pass, n, ntiles));
     }
     FEC_LAUNCH(kStGather, k_gather<<<(unsigned)ntiles, kBlock, 0, st>>>(
-                              xyz, keys0, keys1, vals0, vals1, P, spts, sorig, tile_cnt));
+                              xyz, keys0, keys1, vals0, vals1, colbits, P, spts, sorig,
+                              tile_cnt));
     FEC_LAUNCH(kStTileScan, k_tile_scan<<<1, 1024, 0, st>>>(tile_cnt, tile_off, ntiles, P));
     FEC_LAUNCH(kStCells, k_cells<<<(unsigned)ntiles, kBlock, 0, st>>>(
-                             keys0, keys1, P, tile_off, cell_start, cell_key, cell_col, col_key,
-                             col_cell, cpar, csize, ccanon));
-    FEC_LAUNCH(kStColumnRows, k_colrows<<<nb_cells, kBlock, 0, st>>>(col_key, col_cell,
-                                                                      cell_start, row_start, P));
-    FEC_LAUNCH(kStHookNear, k_hook<0><<<nb_cells, kBlock, 0, st>>>(
-                                spts, cell_start, cell_key, cell_col, col_key, col_cell,
-                                row_start, cpar, P));
+                             keys0, keys1, P, tile_off, cell_start, cell_key, col_key, col_cell,
+                             cpar, csize, ccanon));
+    FEC_LAUNCH(kStColGrid, k_colgrid<<<nb_cells, kBlock, 0, st>>>(col_key, col_cell, cell_start,
+                                                                   colgrid, colbits, P));
+    FEC_LAUNCH(kStRuns, k_runs1<<<(unsigned)ntiles, kBlock, 0, st>>>(spts, cell_start, cell_key,
+                                                                      heads, blkhead, P));
+    FEC_LAUNCH(kStRuns, k_runs2<<<(unsigned)ntiles, kBlock, 0, st>>>(heads, blkhead, cpar, P));
+    FEC_LAUNCH(kStHookNear, k_hook_near<<<nb_cells, kBlock, 0, st>>>(
+                                spts, cell_start, cell_key, col_key, col_cell, colgrid, colbits,
+                                cpar, P));
     FEC_LAUNCH(kStCompress1, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P));
-    FEC_LAUNCH(kStHookFar, k_hook<1><<<nb_cells, kBlock, 0, st>>>(
-                               spts, cell_start, cell_key, cell_col, col_key, col_cell,
-                               row_start, cpar, P));
+    FEC_LAUNCH(kStGiant, k_giant<<<1, 1024, 0, st>>>(cpar, P));
+    FEC_LAUNCH(kStWorkList, k_nongiant<<<nb_cells, kBlock, 0, st>>>(cpar, gbits, work, P));
+    FEC_LAUNCH(kStHookFar, k_hook_far<<<nb_cells, kBlock, 0, st>>>(
+                                spts, cell_start, cell_key, col_key, col_cell, colgrid, colbits,
+                                gbits, work, cpar, P));
     FEC_LAUNCH(kStCompress2, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P));
     FEC_LAUNCH(kStFinalCells, k_final_cells<<<nb_cells, kBlock, 0, st>>>(
                                   cpar, cell_start, sorig, csize, ccanon, P));

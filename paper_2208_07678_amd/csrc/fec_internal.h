@@ -16,6 +16,9 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kMaxPasses = (64 + kRadixBits - 1) / kRadixBits;
 constexpr int kBboxBlocks = 1024;      // max blocks of the bounding-box reduction
 constexpr int kCellBlocks = 4096;      // grid of the grid-stride per-cell kernels
+// Dense column index: one entry per (cx, cy) when the plane has at most
+// kColGridPerPoint entries per point (else columns are binary-searched).
+constexpr int kColGridPerPoint = 8;
 
 // Look-back words of the radix passes: 2-bit flag + 62-bit count.
 constexpr uint64_t kLbAggregate = 1ull << 62;
@@ -50,8 +53,13 @@ struct Params {
     uint64_t idx_mask;
     int64_t M;            // occupied cells
     int64_t Mcol;         // occupied columns (cells sharing cx, cy)
+    int32_t dense_cols;   // 1: column lookups through the dense (cx, cy) index
+    int32_t giant;        // root of the largest component after sampling (-1: none)
+    uint32_t nwork;       // cells outside that component (full-stencil work list)
+    uint32_t pad1;
     int32_t kept;         // kept clusters
     int32_t max_cell;     // largest number of points in one cell
+    unsigned long long counters[8];  // diagnostic event counts (counting builds only)
     uint32_t ticket[kMaxPasses];
     uint32_t hist[kMaxPasses][kRadix];
 };
@@ -61,7 +69,8 @@ struct Layout {
     size_t params, partials, tile_cnt, tile_off;
     size_t keys0, keys1, vals0, vals1, lb0, lb1;
     size_t spts, sorig, cell_start, cell_key, cpar, csize, ccanon;
-    size_t cell_col, col_key, col_cell, row_start;
+    size_t col_key, col_cell, colgrid, colbits, heads, blkhead, gbits, work;
+    uint64_t colgrid_cap;
     size_t total;
     int64_t ntiles;
 };
@@ -102,10 +111,15 @@ inline Layout make_layout(int64_t n) {
     L.cpar = take(un * sizeof(int32_t));
     L.csize = take(un * sizeof(int32_t));
     L.ccanon = take(un * sizeof(int32_t));
-    L.cell_col = take(un * sizeof(uint32_t));
     L.col_key = take(un * sizeof(uint64_t));
     L.col_cell = take((un + 1) * sizeof(uint32_t));
-    L.row_start = take(2 * un * sizeof(uint32_t));
+    L.colgrid_cap = (uint64_t)kColGridPerPoint * un + 1024;
+    L.colgrid = take((size_t)L.colgrid_cap * sizeof(uint32_t));
+    L.colbits = take((size_t)(L.colgrid_cap / 32 + 1) * sizeof(uint32_t));
+    L.heads = take(un);
+    L.blkhead = take((size_t)L.ntiles * sizeof(int32_t));
+    L.gbits = take((un / 64 + 1) * sizeof(uint64_t));
+    L.work = take(un * sizeof(uint32_t));
     L.total = off;
     return L;
 }
@@ -119,9 +133,12 @@ enum Stage : int {
     kStGather,
     kStTileScan,
     kStCells,
-    kStColumnRows,
+    kStColGrid,
+    kStRuns,
     kStHookNear,
     kStCompress1,
+    kStGiant,
+    kStWorkList,
     kStHookFar,
     kStCompress2,
     kStFinalCells,

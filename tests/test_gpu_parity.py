@@ -125,6 +125,30 @@ def test_wide_grid_pair_mode():
     _check(x, 1e-3, 10, 10, "wide grid, size filter")
 
 
+def test_tile_over_lds_capacity():
+    # one column tile holding more cells than the LDS union-find takes
+    # (global union-find inside the tile), near the percolation threshold
+    x = synth.random_cloud(20000, extent=(2.2, 2.2, 20.0), seed=12)
+    _check(x, 0.12, 1, 20000, "tile over capacity")
+    _check(x, 0.12, 3, 50, "tile over capacity, filtered")
+
+
+def test_tile_borders_dense_plane():
+    # a dense plane spanning many column tiles, d such that every cell is
+    # occupied: all joins cross tile borders somewhere
+    x = synth.random_cloud(200000, extent=(40.0, 40.0, 0.05), seed=13)
+    _check(x, 0.15, 1, 200000, "dense plane")
+
+
+def test_flat_plane_single_z_layer():
+    # every point at z = 0 exactly: one cell layer (no z bits in the key)
+    x = synth.random_cloud(30000, extent=(30.0, 30.0, 0.0), seed=14)
+    assert (x[:, 2] == 0).all()
+    _check(x, 0.2, 1, 30000, "flat plane z=0")
+    y = synth.chain_cloud(500, 0.3, axis=1)  # a single line: one column per cell row
+    _check(y, 0.35, 1, 500, "line along y")
+
+
 def test_repeatable_bitwise():
     xyz, d, mn, mx = synth.make_config("lidar120k")
     first, k = gpu_cluster(xyz, d, mn, mx)
