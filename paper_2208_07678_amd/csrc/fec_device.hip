@@ -707,13 +707,31 @@ __global__ __launch_bounds__(kBlock) void k_colgrid(const uint64_t *__restrict__
     }
     if (!P->dense_cols) return;
     const Grid g = grid_of(P);
-    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < Mcol;
-         c += (int64_t)gridDim.x * kBlock) {
-        int64_t cx, cy;
-        g.col_xy(col_key[c], cx, cy);
-        const uint64_t idx = (uint64_t)(cx * g.NY + cy);
-        colgrid[idx] = col_cell[c];
-        atomicOr(&colbits[idx >> 5], 1u << (idx & 31));
+    const int lane = __lane_id();
+    for (int64_t c0 = (int64_t)blockIdx.x * kBlock; c0 < Mcol; c0 += (int64_t)gridDim.x * kBlock) {
+        const int64_t c = c0 + threadIdx.x;
+        const bool valid = c < Mcol;
+        uint64_t idx = 0;
+        if (valid) {
+            int64_t cx, cy;
+            g.col_xy(col_key[c], cx, cy);
+            idx = (uint64_t)(cx * g.NY + cy);
+            colgrid[idx] = col_cell[c];
+        }
+        // columns are sorted, so a wave's bits fall into few words: one
+        // atomic OR per distinct word
+        uint64_t act = __ballot(valid);
+        while (act) {
+            const int l = first_lane(act);
+            const uint64_t w0 = __shfl(idx >> 5, l);
+            const bool mine = valid && (idx >> 5) == w0;
+            const uint64_t grp = __ballot(mine);
+            uint32_t bits = mine ? (1u << (idx & 31)) : 0u;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o);
+            if (lane == l) atomicOr(&colbits[w0], bits);
+            act &= ~grp;
+        }
     }
 }
 
@@ -747,41 +765,52 @@ __device__ __forceinline__ bool find_column(const Grid &g, int64_t cx, int64_t c
 // ------------------------------------------------------------- 8. hooking
 // Union-find over cells; parent[x] <= x always, so a root is the smallest
 // cell of its component.
-__device__ __forceinline__ int32_t uf_find(int32_t *par, int32_t x) {
-    int32_t p = ld_relaxed(par + x);
-    while (p != x) {
-        const int32_t gp = ld_relaxed(par + p);
-        if (gp != p) st_relaxed(par + x, gp);  // path halving; any ancestor is valid
-        x = gp;
-        p = ld_relaxed(par + x);
-    }
-    return x;
-}
-
-__device__ __forceinline__ int32_t uf_find_ro(const int32_t *par, int32_t x) {
-    int32_t p = ld_relaxed(par + x);
+//
+// Parents are read with plain (L2-cached) loads.  The L2s of the XCDs are
+// not coherent with each other inside a kernel, so a read may return an
+// older parent; every older parent is still an ancestor in the same
+// component, which is all the algorithm needs: "same root" answers are
+// always right, "different roots" answers may be stale and cost one extra
+// pair test.  Only the compare-and-swap that hooks a root is coherent, and
+// when it fails the parent it returns (fresh) is where the search resumes,
+// so every retry moves strictly up the tree and the loop ends.
+__device__ __forceinline__ int32_t uf_find(const int32_t *par, int32_t x) {
+    int32_t p = par[x];
     while (p != x) {
         x = p;
-        p = ld_relaxed(par + x);
+        p = par[x];
     }
     return x;
 }
 
-// Joins the components of a and b; returns the root of the union (at the
+// Joins the components of a and b; returns a root of the union (at the
 // time of the join).
 __device__ __forceinline__ int32_t uf_link(int32_t *par, int32_t a, int32_t b) {
-    while (true) {
-        a = uf_find(par, a);
-        b = uf_find(par, b);
-        if (a == b) return a;
-        if (a < b) {
-            const int32_t t = a;
-            a = b;
-            b = t;
+    a = uf_find(par, a);
+    b = uf_find(par, b);
+    while (a != b) {
+        const int32_t hi = a > b ? a : b, lo = a > b ? b : a;
+        // hook the larger root under the smaller one
+        const int32_t old = atomicCAS(par + hi, hi, lo);
+        if (old == hi) return lo;
+        // hi was hooked meanwhile: continue from its current parent
+        if (hi == a) {
+            a = uf_find(par, old);
+        } else {
+            b = uf_find(par, old);
         }
-        // hook the larger root a under the smaller root b
-        if (atomicCAS(par + a, a, b) == a) return b;
     }
+    return a;
+}
+
+// Joins two components whose roots were just read: one CAS when both are
+// still roots, the general loop otherwise.  Returns the root of the union.
+__device__ __forceinline__ int32_t uf_link_roots(int32_t *par, int32_t a, int32_t b) {
+    if (a == b) return a;
+    const int32_t hi = a > b ? a : b, lo = a > b ? b : a;
+    const int32_t old = atomicCAS(par + hi, hi, lo);
+    if (old == hi) return lo;
+    return uf_link(par, old, lo);
 }
 
 // Is there a joined pair between the points [sA, eA) and [sB, eB)?  Stops at
@@ -948,7 +977,7 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
         const uint64_t key = cell_key[A];
         const uint64_t kup = A + 1 < M ? cell_key[A + 1] : ~0ull;
         const uint32_t sA = cell_start[A], eA = cell_start[A + 1];
-        const int32_t p0 = ld_relaxed(cpar + A);
+        const int32_t p0 = cpar[A];
         const uint64_t ck = key >> g.bz;
         const int64_t cz = (int64_t)(key & g.zmask);
         int64_t cx, cy;
@@ -982,7 +1011,7 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
                 const int64_t B = (int64_t)fc[o] + j;
                 kk[o][j] = (has[o] && B < M) ? cell_key[B] : ~0ull;
             }
-        const int32_t q0 = ld_relaxed(cpar + p0);
+        const int32_t q0 = cpar[p0];
         // candidates (existence is tracked explicitly: a key sentinel could
         // equal the wrapped key of a column off the grid)
         uint32_t cm = 0, ovf = 0;
@@ -1004,24 +1033,31 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
 #pragma unroll
         for (int i = 0; i < kCand; ++i) {
             const uint32_t B = i == kCand - 1 ? (uint32_t)A + 1 : fc[i / kNearK] + (uint32_t)(i % kNearK);
-            rb[i] = ((cm >> i) & 1u) ? ld_relaxed(cpar + B) : -1;
+            rb[i] = ((cm >> i) & 1u) ? cpar[B] : -1;
         }
         int32_t ra = (q0 == p0) ? p0 : uf_find(cpar, q0);
         FEC_COUNT(P, 0, __popc(cm));
+        // round 5: point ranges of the candidates in another component
+        uint32_t need = 0;
+        uint32_t sb[kCand], eb[kCand];
 #pragma unroll
         for (int i = 0; i < kCand; ++i) {
-            if (!((cm >> i) & 1u)) continue;
-            int32_t r = rb[i];
-            if (r == ra || r == p0) continue;
-            r = uf_find(cpar, r);
-            if (r == ra) continue;
             const uint32_t B = i == kCand - 1 ? (uint32_t)A + 1 : fc[i / kNearK] + (uint32_t)(i % kNearK);
+            const bool nd = ((cm >> i) & 1u) && rb[i] != ra && rb[i] != p0;
+            need |= (uint32_t)nd << i;
+            sb[i] = nd ? cell_start[B] : 0u;
+            eb[i] = nd ? cell_start[B + 1] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < kCand; ++i) {
+            if (!((need >> i) & 1u)) continue;
+            const int32_t r = uf_find(cpar, rb[i]);
+            if (r == ra) continue;
             FEC_COUNT(P, 1, 1);
-            const uint32_t sB = cell_start[B], eB = cell_start[B + 1];
-            FEC_COUNT(P, 3, (eA - sA) * (eB - sB));
-            if (any_joined(spts, sA, eA, sB, eB, d2)) {
+            FEC_COUNT(P, 3, (eA - sA) * (eb[i] - sb[i]));
+            if (any_joined(spts, sA, eA, sb[i], eb[i], d2)) {
                 FEC_COUNT(P, 2, 1);
-                ra = uf_link(cpar, ra, r);
+                ra = uf_link_roots(cpar, uf_find(cpar, ra), r);
             }
         }
         FEC_COUNT(P, 4, __popc(ovf));
@@ -1045,15 +1081,15 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
     }
 }
 
-// Every cell points at its root afterwards.  Read-only finds, one writer per
-// slot, so no slot is overwritten with a stale ancestor.
+// Every cell points at its root afterwards.  Runs after all joins (data is
+// coherent at the kernel boundary); each slot is written once, with the
+// root, so concurrent finds only ever see ancestors.
 __global__ __launch_bounds__(kBlock) void k_compress(int32_t *cpar, const Params *__restrict__ P) {
     if (P->status != kStatusOk) return;
     const int64_t M = P->M;
     for (int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x; x < M;
          x += (int64_t)gridDim.x * kBlock) {
-        const int32_t r = uf_find_ro(cpar, (int32_t)x);
-        st_relaxed(cpar + x, r);
+        cpar[x] = uf_find(cpar, (int32_t)x);
     }
 }
 
@@ -1175,6 +1211,8 @@ __global__ __launch_bounds__(kBlock) void k_hook_far(const float4 *__restrict__ 
     const int dense = P->dense_cols;
     const float d2 = P->d2;
     const Grid g = grid_of(P);
+    constexpr int kG = 8;      // columns per group (loads issued together)
+    constexpr int kK = 2;      // cells per column loaded up front
     for (uint32_t wi = blockIdx.x * kBlock + threadIdx.x; wi < nwork; wi += gridDim.x * kBlock) {
         const int32_t A = (int32_t)work[wi];
         const uint64_t key = cell_key[A];
@@ -1184,45 +1222,102 @@ __global__ __launch_bounds__(kBlock) void k_hook_far(const float4 *__restrict__ 
         g.col_xy(ck, cx, cy);
         const uint32_t sA = cell_start[A], eA = cell_start[A + 1];
         int32_t ra = uf_find(cpar, A);
-        auto pair = [&](uint32_t B) {
-            const int32_t rb = uf_find(cpar, (int32_t)B);
+        auto pair = [&](uint32_t B, int32_t rb) {
+            if (rb == ra) return;
+            rb = uf_find(cpar, rb);
             if (rb == ra) return;
             if (any_joined(spts, sA, eA, cell_start[B], cell_start[B + 1], d2))
-                ra = uf_link(cpar, ra, rb);
+                ra = uf_link_roots(cpar, uf_find(cpar, ra), rb);
         };
         // own column: the cells two steps down (if giant) and up
         for (int32_t B = A - 1; B >= 0 && B >= A - 2; --B) {
             const uint64_t kb = cell_key[B];
             const int64_t dz = cz - (int64_t)(kb & g.zmask);
             if ((kb >> g.bz) != ck || dz > 2) break;
-            if (dz == 2 && is_giant(gbits, (uint32_t)B)) pair((uint32_t)B);
+            if (dz == 2 && is_giant(gbits, (uint32_t)B)) pair((uint32_t)B, cpar[B]);
         }
         for (int32_t B = A + 1; B < M && B <= A + 2; ++B) {
             const uint64_t kb = cell_key[B];
             const int64_t dz = (int64_t)(kb & g.zmask) - cz;
             if ((kb >> g.bz) != ck || dz > 2) break;
-            if (dz == 2) pair((uint32_t)B);
+            if (dz == 2) pair((uint32_t)B, cpar[B]);
         }
-        for (int dx = -2; dx <= 2; ++dx)
-            for (int dy = -2; dy <= 2; ++dy) {
-                if (dx == 0 && dy == 0) continue;
-                const bool fwd = dx > 0 || (dx == 0 && dy > 0);
-                const bool near_col = dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1;
-                uint32_t f;
-                if (!find_column(g, cx + dx, cy + dy, dense, colgrid, colbits, col_key, col_cell,
-                                 Mcol, f))
-                    continue;
-                const uint64_t want = g.col_key((uint64_t)(cx + dx), (uint64_t)(cy + dy));
-                for (uint32_t B = f; (int64_t)B < M; ++B) {
-                    const uint64_t kb = cell_key[B];
-                    if ((kb >> g.bz) != want) break;
-                    const int64_t dz = (int64_t)(kb & g.zmask) - cz;
-                    if (dz > 2) break;
-                    if (dz < -2) continue;
-                    if (near_col && dz >= -1 && dz <= 1) continue;  // near shell: done
-                    if (fwd || is_giant(gbits, B)) pair(B);
+        // the 24 other columns of the 5x5 neighbourhood, kG at a time
+#pragma unroll 1
+        for (int g0 = 0; g0 < 24; g0 += kG) {
+            int dxs[kG], dys[kG];
+            bool has[kG];
+            uint32_t fc[kG];
+            uint64_t want[kG];
+#pragma unroll
+            for (int o = 0; o < kG; ++o) {
+                int q = g0 + o;
+                q = q >= 12 ? q + 1 : q;  // skip (0, 0)
+                dxs[o] = q / 5 - 2;
+                dys[o] = q % 5 - 2;
+                const int64_t nx = cx + dxs[o], ny = cy + dys[o];
+                want[o] = g.col_key((uint64_t)nx, (uint64_t)ny);
+                if (dense) {
+                    const bool in = nx >= 0 && nx < g.NX && ny >= 0 && ny < g.NY;
+                    const uint64_t idx = in ? (uint64_t)(nx * g.NY + ny) : 0;
+                    const uint32_t wd = in ? colbits[idx >> 5] : 0u;
+                    fc[o] = in ? colgrid[idx] : 0u;
+                    has[o] = (wd >> (idx & 31)) & 1u;
+                } else {
+                    has[o] = find_column(g, nx, ny, 0, colgrid, colbits, col_key, col_cell, Mcol,
+                                         fc[o]);
                 }
             }
+            uint64_t kk[kG][kK];
+#pragma unroll
+            for (int o = 0; o < kG; ++o)
+#pragma unroll
+                for (int j = 0; j < kK; ++j) {
+                    const int64_t B = (int64_t)fc[o] + j;
+                    kk[o][j] = (has[o] && B < M) ? cell_key[B] : 0ull;
+                }
+            uint32_t cm = 0, ovf = 0;
+#pragma unroll
+            for (int o = 0; o < kG; ++o) {
+                const bool near_col = dxs[o] >= -1 && dxs[o] <= 1 && dys[o] >= -1 && dys[o] <= 1;
+                const bool fwd = dxs[o] > 0 || (dxs[o] == 0 && dys[o] > 0);
+#pragma unroll
+                for (int j = 0; j < kK; ++j) {
+                    const bool loaded = has[o] && (int64_t)fc[o] + j < M;
+                    const bool inc = loaded && (kk[o][j] >> g.bz) == want[o];
+                    const int64_t dz = (int64_t)(kk[o][j] & g.zmask) - cz;
+                    const bool inreach = inc && dz >= -2 && dz <= 2 &&
+                                         !(near_col && dz >= -1 && dz <= 1);
+                    // backward pairs only towards the giant component
+                    if (inreach && (fwd || is_giant(gbits, fc[o] + (uint32_t)j)))
+                        cm |= 1u << (o * kK + j);
+                    if (j == kK - 1 && inc && dz < 2) ovf |= 1u << o;
+                }
+            }
+            int32_t rb[kG * kK];
+#pragma unroll
+            for (int i = 0; i < kG * kK; ++i)
+                rb[i] = ((cm >> i) & 1u) ? cpar[fc[i / kK] + (i % kK)] : -1;
+#pragma unroll
+            for (int i = 0; i < kG * kK; ++i)
+                if ((cm >> i) & 1u) pair(fc[i / kK] + (uint32_t)(i % kK), rb[i]);
+            if (ovf) {
+                for (int o = 0; o < kG; ++o) {
+                    if (!((ovf >> o) & 1u)) continue;
+                    const bool near_col =
+                        dxs[o] >= -1 && dxs[o] <= 1 && dys[o] >= -1 && dys[o] <= 1;
+                    const bool fwd = dxs[o] > 0 || (dxs[o] == 0 && dys[o] > 0);
+                    for (uint32_t B = fc[o] + kK; (int64_t)B < M; ++B) {
+                        const uint64_t kb = cell_key[B];
+                        if ((kb >> g.bz) != want[o]) break;
+                        const int64_t dz = (int64_t)(kb & g.zmask) - cz;
+                        if (dz > 2) break;
+                        if (dz < -2 || (near_col && dz >= -1 && dz <= 1)) continue;
+                        if (fwd || is_giant(gbits, B)) pair(B, cpar[B]);
+                    }
+                }
+            }
+        }
     }
 }
 
