@@ -1223,9 +1223,12 @@ __global__ __launch_bounds__(kBlock) void k_hook_far(const float4 *__restrict__ 
         const uint32_t sA = cell_start[A], eA = cell_start[A + 1];
         int32_t ra = uf_find(cpar, A);
         auto pair = [&](uint32_t B, int32_t rb) {
+            FEC_COUNT(P, 5, 1);
             if (rb == ra) return;
             rb = uf_find(cpar, rb);
             if (rb == ra) return;
+            FEC_COUNT(P, 6, 1);
+            FEC_COUNT(P, 7, (eA - sA) * (cell_start[B + 1] - cell_start[B]));
             if (any_joined(spts, sA, eA, cell_start[B], cell_start[B + 1], d2))
                 ra = uf_link_roots(cpar, uf_find(cpar, ra), rb);
         };
