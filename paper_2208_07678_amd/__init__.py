@@ -54,6 +54,7 @@ def _load():
         "fec_workspace_bytes": ([i64], ctypes.c_size_t),
         "fec_cluster_async": ([vp, i64, f32, i32, i32, vp, vp, vp, ctypes.c_size_t, vp], i32),
         "fec_set_stream": ([vp], i32),
+        "fec_set_hooking": ([i32], i32),
         "fec_release": ([], None),
         "fec_last_error": ([], ctypes.c_char_p),
         "fec_version": ([], ctypes.c_char_p),
@@ -73,14 +74,16 @@ def _load():
 
 
 EXPORTED = [
-    "fec_cluster", "fec_workspace_bytes", "fec_cluster_async", "fec_set_stream", "fec_release",
+    "fec_cluster", "fec_workspace_bytes", "fec_cluster_async", "fec_set_stream",
+    "fec_set_hooking", "fec_release",
     "fec_last_error", "fec_version", "fec_workspace_stats", "fec_profile_enable",
     "fec_profile_read", "fec_profile_reset", "fec_stage_count", "fec_stage_name",
 ]
 
 STATS_FIELDS = ["n", "finite_points", "cells", "columns", "key_bits", "radix_passes",
                 "grid_x", "grid_y", "grid_z", "max_points_per_cell", "status",
-                "work_cells", "giant_root"] + ["counter%d" % i for i in range(8)]
+                "work_cells", "giant_root", "tiles", "subtiles",
+                "cell_pass_subtiles", "tile_edges"] + ["counter%d" % i for i in range(8)]
 
 
 class FecError(RuntimeError):
@@ -91,6 +94,19 @@ class FecError(RuntimeError):
 
 def _raise(code: int):
     raise FecError(code, (_load().fec_last_error() or b"").decode())
+
+
+HOOK_CELLS = 0
+HOOK_TILES = 1
+
+
+def set_hooking(mode: int) -> int:
+    """Selects per-cell (HOOK_CELLS) or tile (HOOK_TILES) hooking for later
+    calls; returns the previous mode."""
+    rc = _load().fec_set_hooking(int(mode))
+    if rc < 0:
+        _raise(rc)
+    return rc
 
 
 def version() -> str:

@@ -44,6 +44,7 @@ struct Params {
     double ox, oy, oz; // grid origin: the bounding box minimum of finite points
     double inv_s;      // 1 / cell side
     int64_t NX, NY, NZ;
+    int64_t NYp;          // row stride of the dense column index: NY rounded up to 32
     int32_t bx, by, bz;   // key bits per axis: key = cx << (by+bz) | cy << bz | cz
     int32_t key_bits;     // bits sorted (grid key, plus one for non-finite points)
     int32_t idx_bits;     // bits of the point index packed below the key
@@ -57,6 +58,13 @@ struct Params {
     int32_t giant;        // root of the largest component after sampling (-1: none)
     uint32_t nwork;       // cells outside that component (full-stencil work list)
     uint32_t pad1;
+    uint32_t ntile;       // occupied tiles (dense index)
+    uint32_t nsub;        // tile rows re-run one at a time (tiles over the LDS capacity)
+    uint32_t nglob;       // tile rows over the LDS capacity (cell-by-cell pass)
+    int32_t use_tiles;    // 1: hooking by tiles in LDS (dense index), 0: per cell
+    uint32_t ticket_tile[2][8];  // work counters of the tile kernels (per level)
+    uint32_t nedges;      // cross-tile links left by the tile kernels
+    uint32_t pad3;
     int32_t kept;         // kept clusters
     int32_t max_cell;     // largest number of points in one cell
     unsigned long long counters[8];  // diagnostic event counts (counting builds only)
@@ -69,7 +77,8 @@ struct Layout {
     size_t params, partials, tile_cnt, tile_off;
     size_t keys0, keys1, vals0, vals1, lb0, lb1;
     size_t spts, sorig, cell_start, cell_key, cpar, csize, ccanon;
-    size_t col_key, col_cell, colgrid, colbits, heads, blkhead, gbits, work;
+    size_t col_key, col_cell, colgrid, colbits, heads, blkhead, gbits, work, edges;
+    uint64_t edge_cap;
     uint64_t colgrid_cap;
     size_t total;
     int64_t ntiles;
@@ -115,11 +124,14 @@ inline Layout make_layout(int64_t n) {
     L.col_cell = take((un + 1) * sizeof(uint32_t));
     L.colgrid_cap = (uint64_t)kColGridPerPoint * un + 1024;
     L.colgrid = take((size_t)L.colgrid_cap * sizeof(uint32_t));
-    L.colbits = take((size_t)(L.colgrid_cap / 32 + 1) * sizeof(uint32_t));
+    L.colbits = take((size_t)(L.colgrid_cap / 32 + 2) * sizeof(uint32_t));
     L.heads = take(un);
     L.blkhead = take((size_t)L.ntiles * sizeof(int32_t));
     L.gbits = take((un / 64 + 1) * sizeof(uint64_t));
     L.work = take(un * sizeof(uint32_t));
+    L.edge_cap = 2 * (uint64_t)un;  // links between tiles (tile hooking only)
+    if (L.edge_cap > 0xFFFFFFFFull) L.edge_cap = 0xFFFFFFFFull;
+    L.edges = take((size_t)L.edge_cap * sizeof(uint64_t));
     L.total = off;
     return L;
 }
@@ -134,6 +146,11 @@ enum Stage : int {
     kStTileScan,
     kStCells,
     kStColGrid,
+    kStTileList,
+    kStHookTile,
+    kStHookRows,
+    kStLinkEdges,
+    kStHookCells,
     kStRuns,
     kStHookNear,
     kStCompress1,
@@ -157,8 +174,10 @@ struct Timer {
 };
 
 // Enqueues the whole pipeline.  Returns hipSuccess or the first launch error.
+// hook_tiles: 1 = hook by tiles in LDS where the dense column index applies,
+// 0 = per cell everywhere.
 hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_size,
                            int32_t max_size, int32_t *labels_out, int32_t *k_out, void *ws,
-                           const Layout &L, hipStream_t stream, Timer *timer);
+                           const Layout &L, hipStream_t stream, Timer *timer, int hook_tiles);
 
 }  // namespace fec

@@ -14,6 +14,7 @@ from .clouds import (  # noqa: F401
     random_cloud,
     near_threshold_cloud,
     chain_cloud,
+    blob_lattice,
     CONFIGS,
     make_config,
 )

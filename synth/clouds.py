@@ -415,6 +415,27 @@ def random_cloud(n: int, extent=(10.0, 10.0, 10.0), seed: int = 0, offset=(0.0, 
     return np.ascontiguousarray(p.astype(np.float32))
 
 
+def blob_lattice(extent=(6.0, 6.0), spacing: float = 0.22, jitter: float = 0.02,
+                 pts_per_blob: int = 30, radius: float = 0.01, layers: int = 1, seed: int = 0,
+                 origin=(0.0, 0.0, 0.0)):
+    """Tight blobs on a jittered lattice: `layers` planes of blobs `spacing`
+    apart in x, y and z, each blob `pts_per_blob` points uniform in a cube of
+    half-side `radius` around its centre (float32, shuffled).  With a
+    spacing near the clustering distance about half of the neighbouring
+    blobs end up within reach of each other, so a dense patch holds many
+    clusters of varied shapes."""
+    rng = np.random.default_rng(seed)
+    nx = max(1, int(extent[0] / spacing))
+    ny = max(1, int(extent[1] / spacing))
+    gx, gy, gz = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(layers), indexing="ij")
+    centres = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], axis=1) * spacing
+    centres = centres + rng.uniform(-jitter, jitter, size=centres.shape) + np.asarray(origin)
+    pts = np.repeat(centres, pts_per_blob, axis=0)
+    pts = pts + rng.uniform(-radius, radius, size=pts.shape)
+    pts = pts[rng.permutation(pts.shape[0])]
+    return np.ascontiguousarray(pts.astype(np.float32))
+
+
 def chain_cloud(n: int, spacing: float, axis: int = 0, origin=(0.0, 0.0, 0.0)):
     """Collinear points p_k = origin + k * spacing * e_axis (float32)."""
     p = np.zeros((n, 3))

@@ -85,3 +85,15 @@ def test_workspace_stats_and_profile():
     assert st["n"] == xyz.shape[0] and st["finite_points"] == xyz.shape[0]
     assert 0 < st["cells"] <= xyz.shape[0] and st["status"] == 0
     assert prof["hook_near"][1] == 1 and prof["hook_near"][0] > 0
+
+
+def test_hooking_mode_switch():
+    import paper_2208_07678_amd as fec
+    prev = fec.set_hooking(fec.HOOK_TILES)
+    try:
+        with pytest.raises(fec.FecError) as ei:
+            fec.set_hooking(7)
+        assert ei.value.code == fec.FEC_EINVAL
+        assert fec.set_hooking(fec.HOOK_TILES) == fec.HOOK_TILES
+    finally:
+        fec.set_hooking(prev)
