@@ -376,6 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(const float *__restrict__ xyz,
 // already running.  The wait is bounded; on timeout the call fails with a
 // device status instead of hanging.
 constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr int kLookBack = 8;  // predecessor tiles read per look-back round trip
 
 __global__ __launch_bounds__(kBlock) void k_sort_pass(const uint64_t *__restrict__ src,
                                                       uint64_t *__restrict__ dst,
@@ -389,8 +390,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(const uint64_t *__restrict
     __shared__ uint32_t s_cnt[kBlock / 64][kRadix];
     __shared__ uint32_t s_base[kRadix];
     __shared__ uint32_t s_local[kRadix];
-    __shared__ uint64_t s_buf[kTile];
-    __shared__ uint32_t s_vbuf[kTile];
+    __shared__ uint64_t s_buf[kTile];  // keys in digit order (values after them in pair mode)
     __shared__ uint32_t s_tmp[kBlock / 64];
     __shared__ uint32_t s_tile;
     __shared__ int s_fail;
@@ -400,11 +400,17 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(const uint64_t *__restrict
          w += (int64_t)gridDim.x * kBlock)
         lb_next[w] = 0;
     for (int i = tid; i < (kBlock / 64) * kRadix; i += kBlock) (&s_cnt[0][0])[i] = 0;
+#ifdef FEC_SORT_TIMING
+    const uint64_t t_start = wall_clock64();
+#endif
     if (tid == 0) {
         s_tile = atomicAdd(&P->ticket[pass], 1u);
         s_fail = 0;
     }
     __syncthreads();
+#ifdef FEC_SORT_TIMING
+    const uint64_t t_ticket = wall_clock64();
+#endif
     const int64_t tile = s_tile;
     const int shift = P->key_shift + pass * kRadixBits;
     const bool pair = P->pair_mode != 0;
@@ -450,28 +456,45 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(const uint64_t *__restrict
         st_relaxed(mine, kLbInclusive | (uint64_t)tcount);
     } else {
         st_relaxed(mine, kLbAggregate | (uint64_t)tcount);
+        // look back kLookBack predecessors per round trip: add aggregates
+        // until an inclusive prefix; stall (and reload) at a tile that has
+        // not published yet.  Tile 0 always publishes an inclusive prefix.
         int64_t j = tile - 1;
         uint32_t spins = 0;
         while (true) {
-            const uint64_t w = ld_relaxed(lb_cur + j * kRadix + tid);
-            const uint64_t f = w & ~kLbValue;
-            if (f == 0) {
+            uint64_t w[kLookBack];
+#pragma unroll
+            for (int q = 0; q < kLookBack; ++q)
+                w[q] = j - q >= 0 ? ld_relaxed(lb_cur + (j - q) * kRadix + tid) : kLbInclusive;
+            int used = 0;
+            bool done = false, stall = false;
+#pragma unroll
+            for (int q = 0; q < kLookBack; ++q) {
+                if (done || stall) continue;
+                const uint64_t f = w[q] & ~kLbValue;
+                if (f == 0) {
+                    stall = true;
+                    continue;
+                }
+                excl += w[q] & kLbValue;
+                ++used;
+                if (f == kLbInclusive) done = true;
+            }
+            if (done) break;
+            j -= used;
+            if (stall) {
                 if (++spins > kSpinLimit) {
                     s_fail = 1;
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
-                continue;
-            }
-            excl += w & kLbValue;
-            if (f == kLbInclusive) break;
-            if (--j < 0) {
-                s_fail = 1;
-                break;
             }
         }
         st_relaxed(mine, kLbInclusive | (excl + tcount));
     }
+#ifdef FEC_SORT_TIMING
+    const uint64_t t_lb = wall_clock64();
+#endif
     // global digit base (exclusive scan of the pass histogram plus the
     // tiles before this one) and tile-local digit base
     uint32_t tot;
@@ -486,29 +509,60 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(const uint64_t *__restrict
         return;
     }
     // stage the tile in LDS in digit order, then write each digit's run
-    // contiguously
+    // contiguously; in pair mode the values follow through the same buffer
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const int64_t e = base + k * 64 + lane;
         if (e < n) {
             const uint32_t dg = (uint32_t)(v[k] >> shift) & (kRadix - 1);
-            const uint32_t lp = s_local[dg] + s_cnt[wave][dg] + rk[k];
-            s_buf[lp] = v[k];
-            if (pair) s_vbuf[lp] = srcv[e];
+            s_buf[s_local[dg] + s_cnt[wave][dg] + rk[k]] = v[k];
         }
     }
     __syncthreads();
     const int64_t rem = n - tile * kTile;
     const int tile_n = rem < kTile ? (int)rem : kTile;
-    for (int j = tid; j < tile_n; j += kBlock) {
-        const uint64_t w = s_buf[j];
-        const uint32_t dg = (uint32_t)(w >> shift) & (kRadix - 1);
-        const uint64_t pos = (uint64_t)s_base[dg] + (uint32_t)(j - s_local[dg]);
-        if (pos < (uint64_t)n) {
-            dst[pos] = w;
-            if (pair) dstv[pos] = s_vbuf[j];
+    uint32_t pos[kItems];  // n < 2^31
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        const int j = tid + i * kBlock;
+        pos[i] = 0xFFFFFFFFu;
+        if (j < tile_n) {
+            const uint64_t w = s_buf[j];
+            const uint32_t dg = (uint32_t)(w >> shift) & (kRadix - 1);
+            const uint64_t p = (uint64_t)s_base[dg] + (uint32_t)(j - s_local[dg]);
+            if (p < (uint64_t)n) {
+                pos[i] = (uint32_t)p;
+                dst[p] = w;
+            }
         }
     }
+    if (pair) {
+        uint32_t *s_vbuf = reinterpret_cast<uint32_t *>(s_buf);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const int64_t e = base + k * 64 + lane;
+            if (e < n) {
+                const uint32_t dg = (uint32_t)(v[k] >> shift) & (kRadix - 1);
+                s_vbuf[s_local[dg] + s_cnt[wave][dg] + rk[k]] = srcv[e];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const int j = tid + i * kBlock;
+            if (pos[i] != 0xFFFFFFFFu) dstv[pos[i]] = s_vbuf[j];
+        }
+    }
+#ifdef FEC_SORT_TIMING
+    if (tid == 0) {
+        const uint64_t t_end = wall_clock64();
+        atomicAdd(&P->counters[0], (unsigned long long)(t_ticket - t_start));
+        atomicAdd(&P->counters[1], (unsigned long long)(t_lb - t_ticket));
+        atomicAdd(&P->counters[2], (unsigned long long)(t_end - t_lb));
+        atomicAdd(&P->counters[3], 1ull);
+    }
+#endif
 }
 
 // ------------------------------------------------------------- 5. gather
@@ -1033,6 +1087,7 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
         const int64_t cz = (int64_t)(key & g.zmask);
         int64_t cx, cy;
         g.col_xy(ck, cx, cy);
+        const float4 pa = spts[sA];  // A's first point, for the one-pair tests
         // round 2: neighbour columns
         bool has[kC];
         uint32_t fc[kC];
@@ -1080,25 +1135,28 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
                 if (j == kNearK - 1 && inc && dz < 1) ovf |= 1u << o;
             }
         }
-        // round 4: parents of the candidates
+        // round 4: parents and point ranges of the candidates
         int32_t rb[kCand];
-#pragma unroll
-        for (int i = 0; i < kCand; ++i) {
-            const uint32_t B = i == kCand - 1 ? (uint32_t)A + 1 : fc[i / kNearK] + (uint32_t)(i % kNearK);
-            rb[i] = ((cm >> i) & 1u) ? cpar[B] : -1;
-        }
-        int32_t ra = (q0 == p0) ? p0 : uf_find(cpar, q0);
-        FEC_COUNT(P, 0, __popc(cm));
-        // round 5: point ranges of the candidates in another component
-        uint32_t need = 0;
         uint32_t sb[kCand], eb[kCand];
 #pragma unroll
         for (int i = 0; i < kCand; ++i) {
             const uint32_t B = i == kCand - 1 ? (uint32_t)A + 1 : fc[i / kNearK] + (uint32_t)(i % kNearK);
+            const bool c = (cm >> i) & 1u;
+            rb[i] = c ? cpar[B] : -1;
+            sb[i] = c ? cell_start[B] : 0u;
+            eb[i] = c ? cell_start[B + 1] : 0u;
+        }
+        int32_t ra = (q0 == p0) ? p0 : uf_find(cpar, q0);
+        FEC_COUNT(P, 0, __popc(cm));
+        // round 5: the first point of every candidate in another component,
+        // tested against A's first point all at once; that one pair decides
+        // most joined cell pairs, the others are scanned in full below
+        uint32_t need = 0, quick = 0;
+#pragma unroll
+        for (int i = 0; i < kCand; ++i) {
             const bool nd = ((cm >> i) & 1u) && rb[i] != ra && rb[i] != p0;
             need |= (uint32_t)nd << i;
-            sb[i] = nd ? cell_start[B] : 0u;
-            eb[i] = nd ? cell_start[B + 1] : 0u;
+            if (nd) quick |= (uint32_t)joined(pa.x, pa.y, pa.z, spts[sb[i]], d2) << i;
         }
 #pragma unroll
         for (int i = 0; i < kCand; ++i) {
@@ -1107,7 +1165,7 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
             if (r == ra) continue;
             FEC_COUNT(P, 1, 1);
             FEC_COUNT(P, 3, (eA - sA) * (eb[i] - sb[i]));
-            if (any_joined(spts, sA, eA, sb[i], eb[i], d2)) {
+            if (((quick >> i) & 1u) || any_joined(spts, sA, eA, sb[i], eb[i], d2)) {
                 FEC_COUNT(P, 2, 1);
                 ra = uf_link_roots(cpar, uf_find(cpar, ra), r);
             }
@@ -1201,8 +1259,10 @@ __global__ __launch_bounds__(1024) void k_giant(const int32_t *__restrict__ cpar
 }
 
 // Bitmap of the cells in the giant component (after the near shell) and
-// the list of the others (the far-shell work list); the list append is
-// aggregated per block.
+// the list of the others (the far-shell work list).  Each block takes one
+// contiguous chunk of cells: it counts its list entries, reserves them with
+// one atomic, then writes them (a counter bumped per 256 cells would be a
+// hot spot).
 __global__ __launch_bounds__(kBlock) void k_nongiant(const int32_t *__restrict__ cpar,
                                                      uint64_t *__restrict__ gbits,
                                                      uint32_t *__restrict__ work,
@@ -1213,27 +1273,46 @@ __global__ __launch_bounds__(kBlock) void k_nongiant(const int32_t *__restrict__
     const int64_t M = P->M;
     const int32_t giant = P->giant;
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
-    for (int64_t b0 = (int64_t)blockIdx.x * kBlock; b0 < M; b0 += (int64_t)gridDim.x * kBlock) {
+    // chunk of whole 256-cell groups (keeps the bitmap words aligned)
+    const int64_t groups = (M + kBlock - 1) / kBlock;
+    const int64_t per = (groups + gridDim.x - 1) / gridDim.x;
+    const int64_t c0 = (int64_t)blockIdx.x * per * kBlock;
+    const int64_t c1 = c0 + per * kBlock < M ? c0 + per * kBlock : M;
+    if (c0 >= c1) return;
+    uint32_t mine = 0;
+    for (int64_t b0 = c0; b0 < c1; b0 += kBlock) {
         const int64_t A = b0 + threadIdx.x;
-        const bool valid = A < M;
+        const bool valid = A < c1;
         const bool gi = valid && cpar[A] == giant;
         const uint64_t gm = __ballot(gi);
         if (lane == 0 && valid) gbits[A >> 6] = gm;  // A is 64-aligned on lane 0
-        const bool w = valid && !gi;
+        mine += (valid && !gi) ? 1u : 0u;
+    }
+    mine = wave_sum(mine);
+    if (lane == 0) s_wcnt[wave] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int i = 0; i < kBlock / 64; ++i) tot += s_wcnt[i];
+        s_base = tot ? atomicAdd(&P->nwork, tot) : 0u;
+    }
+    __syncthreads();
+    uint32_t base = s_base;
+    for (int64_t b0 = c0; b0 < c1; b0 += kBlock) {
+        const int64_t A = b0 + threadIdx.x;
+        const bool valid = A < c1;
+        const bool w = valid && cpar[A] != giant;
         const uint64_t wm = __ballot(w);
         if (lane == 0) s_wcnt[wave] = (uint32_t)__popcll(wm);
         __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t tot = 0;
-            for (int i = 0; i < kBlock / 64; ++i) {
-                const uint32_t c = s_wcnt[i];
-                s_wcnt[i] = tot;
-                tot += c;
-            }
-            s_base = tot ? atomicAdd(&P->nwork, tot) : 0u;
+        uint32_t before = 0, tot = 0;
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; ++i) {
+            before += i < wave ? s_wcnt[i] : 0u;
+            tot += s_wcnt[i];
         }
-        __syncthreads();
-        if (w) work[s_base + s_wcnt[wave] + (uint32_t)__popcll(wm & lanemask_lt())] = (uint32_t)A;
+        if (w) work[base + before + (uint32_t)__popcll(wm & lanemask_lt())] = (uint32_t)A;
+        base += tot;
         __syncthreads();
     }
 }
