@@ -33,7 +33,8 @@ HBM_PEAK_GBS = 8000.0
 ALG_BYTES_PER_POINT = {
     "bbox": 12.0,        # read xyz
     "keys": 12.0 + 8.0,  # read xyz, write packed key
-    "sort_pass": 16.0,   # read + write one 8-byte packed key per pass
+    "sort_hist": 8.0,     # read one 8-byte packed key per pass
+    "sort_scatter": 16.0,  # read + write one 8-byte packed key per pass
     "gather": 8.0 + 12.0 + 16.0 + 4.0,  # read key, read xyz, write float4 + index
     "final_labels": 4.0 + 4.0,  # read original index, write label
 }

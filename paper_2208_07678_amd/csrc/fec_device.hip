@@ -76,16 +76,6 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     return v;
 }
 
-template <class T>
-__device__ __forceinline__ T ld_relaxed(const T *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-template <class T>
-__device__ __forceinline__ void st_relaxed(T *p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __device__ __forceinline__ int bits_for(int64_t v) {  // bits to hold 0 .. v-1
     return v <= 1 ? 0 : 64 - __clzll((unsigned long long)(v - 1));
 }
@@ -231,7 +221,6 @@ __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ parti
         sc[wave] = cnt;
     }
     for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kBlock) (&P->hist[0][0])[i] = 0;
-    if (threadIdx.x < kMaxPasses) P->ticket[threadIdx.x] = 0;
     if (threadIdx.x < 8) P->counters[threadIdx.x] = 0;
     __syncthreads();
     if (threadIdx.x != 0) return;
@@ -314,8 +303,7 @@ __device__ __forceinline__ uint64_t make_key(uint64_t cx, uint64_t cy, uint64_t 
 __global__ __launch_bounds__(kBlock) void k_keys(const float *__restrict__ xyz,
                                                  Params *__restrict__ P,
                                                  uint64_t *__restrict__ keys,
-                                                 uint32_t *__restrict__ vals,
-                                                 uint64_t *__restrict__ lb0, int64_t lb_words) {
+                                                 uint32_t *__restrict__ vals) {
     __shared__ uint32_t sh[kMaxPasses][kRadix];
     if (P->status != kStatusOk) return;
     for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kBlock) (&sh[0][0])[i] = 0;
@@ -364,54 +352,119 @@ __global__ __launch_bounds__(kBlock) void k_keys(const float *__restrict__ xyz,
         const uint32_t v = (&sh[0][0])[i];
         if (v) atomicAdd(&(&P->hist[0][0])[i], v);
     }
-    for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < lb_words;
-         w += (int64_t)gridDim.x * kBlock)
-        lb0[w] = 0;
 }
 
 // ------------------------------------------------------------- 4. sort
-// One stable LSD radix pass over the packed (key, index) words with a
-// decoupled look-back across tiles.  Tiles are claimed in launch order from
-// a counter, so every tile a block waits for belongs to a block that is
-// already running.  The wait is bounded; on timeout the call fails with a
-// device status instead of hanging.
-constexpr uint32_t kSpinLimit = 1u << 22;
-constexpr int kLookBack = 8;  // predecessor tiles read per look-back round trip
+// Stable LSD radix sort of the packed (key, index) words, kRadixBits per
+// pass, reduce-then-scan: (1) each tile of kTile words counts its digits,
+// (2) one block per digit turns the per-tile counts (digit-major) into the
+// global position of that digit's first word in every tile, (3) each tile
+// ranks its words stably, stages them in LDS in digit order and writes each
+// digit's run to its position.  Tiles are independent in every step.
 
-__global__ __launch_bounds__(kBlock) void k_sort_pass(const uint64_t *__restrict__ src,
-                                                      uint64_t *__restrict__ dst,
-                                                      const uint32_t *__restrict__ srcv,
-                                                      uint32_t *__restrict__ dstv,
-                                                      Params *__restrict__ P,
-                                                      uint64_t *__restrict__ lb_cur,
-                                                      uint64_t *__restrict__ lb_next, int pass,
-                                                      int64_t n, int64_t ntiles) {
+// Digit and stable in-wave rank of item k of this wave (lanes with equal
+// digits are "peers"; the rank counts peers on lower lanes).
+__device__ __forceinline__ uint64_t digit_peers(uint32_t dg, bool valid) {
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+        const bool bit = (dg >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        peers &= bit ? bb : ~bb;
+    }
+    return peers;
+}
+
+// (1) per-tile digit counts, stored digit-major: th[dg * ntiles + tile].
+__global__ __launch_bounds__(kBlock) void k_sort_hist(const uint64_t *__restrict__ src,
+                                                      const Params *__restrict__ P, int pass,
+                                                      int64_t n, int64_t ntiles,
+                                                      uint32_t *__restrict__ th) {
+    if (pass >= P->npasses || P->status != kStatusOk) return;
+    __shared__ uint32_t s_cnt[kBlock / 64][kRadix];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = __lane_id();
+    for (int i = tid; i < (kBlock / 64) * kRadix; i += kBlock) (&s_cnt[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t tile = blockIdx.x;
+    const int shift = P->key_shift + pass * kRadixBits;
+    const int64_t base = tile * kTile + (int64_t)wave * (64 * kItems);
+    uint64_t v[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int64_t e = base + k * 64 + lane;
+        v[k] = e < n ? src[e] : 0ull;
+    }
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const bool valid = base + k * 64 + lane < n;
+        const uint32_t dg = (uint32_t)(v[k] >> shift) & (kRadix - 1);
+        const uint64_t peers = digit_peers(dg, valid);
+        if (valid && (peers & lanemask_lt()) == 0) s_cnt[wave][dg] += (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) c += s_cnt[w][tid];
+    th[(int64_t)tid * ntiles + tile] = c;
+}
+
+// (2) one block per digit: exclusive scan of the digit's per-tile counts
+// plus the digit's global base (the counts of all smaller digits).
+__global__ __launch_bounds__(kBlock) void k_sort_scan(const Params *__restrict__ P, int pass,
+                                                      int64_t ntiles, uint32_t *__restrict__ th) {
+    if (pass >= P->npasses || P->status != kStatusOk) return;
+    __shared__ uint32_t s_tmp[kBlock / 64];
+    __shared__ uint32_t s_carry;
+    const int d = blockIdx.x, tid = threadIdx.x;
+    uint32_t tot;
+    const uint32_t hb = block_excl_scan(P->hist[pass][tid], s_tmp, tot);
+    if (tid == d) s_carry = hb;
+    __syncthreads();
+    uint32_t *row = th + (int64_t)d * ntiles;
+    for (int64_t c0 = 0; c0 < ntiles; c0 += kTile) {
+        // kItems consecutive counts per thread
+        uint32_t v[kItems], sum = 0;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const int64_t i = c0 + (int64_t)tid * kItems + k;
+            v[k] = i < ntiles ? row[i] : 0u;
+            sum += v[k];
+        }
+        const uint32_t carry = s_carry;
+        __syncthreads();
+        const uint32_t before = block_excl_scan(sum, s_tmp, tot);
+        uint32_t run = carry + before;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const int64_t i = c0 + (int64_t)tid * kItems + k;
+            if (i < ntiles) row[i] = run;
+            run += v[k];
+        }
+        __syncthreads();
+        if (tid == 0) s_carry = carry + tot;
+        __syncthreads();
+    }
+}
+
+// (3) stable scatter of one tile.
+__global__ __launch_bounds__(kBlock) void k_sort_scatter(const uint64_t *__restrict__ src,
+                                                         uint64_t *__restrict__ dst,
+                                                         const uint32_t *__restrict__ srcv,
+                                                         uint32_t *__restrict__ dstv,
+                                                         const Params *__restrict__ P, int pass,
+                                                         int64_t n, int64_t ntiles,
+                                                         const uint32_t *__restrict__ th) {
     if (pass >= P->npasses || P->status != kStatusOk) return;
     __shared__ uint32_t s_cnt[kBlock / 64][kRadix];
     __shared__ uint32_t s_base[kRadix];
     __shared__ uint32_t s_local[kRadix];
     __shared__ uint64_t s_buf[kTile];  // keys in digit order (values after them in pair mode)
     __shared__ uint32_t s_tmp[kBlock / 64];
-    __shared__ uint32_t s_tile;
-    __shared__ int s_fail;
     const int tid = threadIdx.x, wave = tid >> 6, lane = __lane_id();
-
-    for (int64_t w = (int64_t)blockIdx.x * kBlock + tid; w < ntiles * kRadix;
-         w += (int64_t)gridDim.x * kBlock)
-        lb_next[w] = 0;
     for (int i = tid; i < (kBlock / 64) * kRadix; i += kBlock) (&s_cnt[0][0])[i] = 0;
-#ifdef FEC_SORT_TIMING
-    const uint64_t t_start = wall_clock64();
-#endif
-    if (tid == 0) {
-        s_tile = atomicAdd(&P->ticket[pass], 1u);
-        s_fail = 0;
-    }
+    const int64_t tile = blockIdx.x;
+    s_base[tid] = th[(int64_t)tid * ntiles + tile];
     __syncthreads();
-#ifdef FEC_SORT_TIMING
-    const uint64_t t_ticket = wall_clock64();
-#endif
-    const int64_t tile = s_tile;
     const int shift = P->key_shift + pass * kRadixBits;
     const bool pair = P->pair_mode != 0;
     const int64_t base = tile * kTile + (int64_t)wave * (64 * kItems);
@@ -427,20 +480,13 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(const uint64_t *__restrict
     for (int k = 0; k < kItems; ++k) {
         const bool valid = base + k * 64 + lane < n;
         const uint32_t dg = (uint32_t)(v[k] >> shift) & (kRadix - 1);
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
-            const bool bit = (dg >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            peers &= bit ? bb : ~bb;
-        }
+        const uint64_t peers = digit_peers(dg, valid);
         const uint32_t below = (uint32_t)__popcll(peers & lanemask_lt());
         const uint32_t prev = s_cnt[wave][dg];
         rk[k] = prev + below;
         if (valid && below == 0) s_cnt[wave][dg] = prev + (uint32_t)__popcll(peers);
     }
     __syncthreads();
-
     // per digit (thread = digit): wave offsets inside the tile, tile count
     uint32_t run = 0;
 #pragma unroll
@@ -449,65 +495,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(const uint64_t *__restrict
         s_cnt[w][tid] = run;
         run += c;
     }
-    const uint32_t tcount = run;
-    uint64_t *mine = lb_cur + tile * kRadix + tid;
-    uint64_t excl = 0;
-    if (tile == 0) {
-        st_relaxed(mine, kLbInclusive | (uint64_t)tcount);
-    } else {
-        st_relaxed(mine, kLbAggregate | (uint64_t)tcount);
-        // look back kLookBack predecessors per round trip: add aggregates
-        // until an inclusive prefix; stall (and reload) at a tile that has
-        // not published yet.  Tile 0 always publishes an inclusive prefix.
-        int64_t j = tile - 1;
-        uint32_t spins = 0;
-        while (true) {
-            uint64_t w[kLookBack];
-#pragma unroll
-            for (int q = 0; q < kLookBack; ++q)
-                w[q] = j - q >= 0 ? ld_relaxed(lb_cur + (j - q) * kRadix + tid) : kLbInclusive;
-            int used = 0;
-            bool done = false, stall = false;
-#pragma unroll
-            for (int q = 0; q < kLookBack; ++q) {
-                if (done || stall) continue;
-                const uint64_t f = w[q] & ~kLbValue;
-                if (f == 0) {
-                    stall = true;
-                    continue;
-                }
-                excl += w[q] & kLbValue;
-                ++used;
-                if (f == kLbInclusive) done = true;
-            }
-            if (done) break;
-            j -= used;
-            if (stall) {
-                if (++spins > kSpinLimit) {
-                    s_fail = 1;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
-        st_relaxed(mine, kLbInclusive | (excl + tcount));
-    }
-#ifdef FEC_SORT_TIMING
-    const uint64_t t_lb = wall_clock64();
-#endif
-    // global digit base (exclusive scan of the pass histogram plus the
-    // tiles before this one) and tile-local digit base
     uint32_t tot;
-    const uint32_t hb = block_excl_scan(P->hist[pass][tid], s_tmp, tot);
-    s_base[tid] = hb + (uint32_t)excl;
+    s_local[tid] = block_excl_scan(run, s_tmp, tot);
     __syncthreads();
-    const uint32_t lb = block_excl_scan(tcount, s_tmp, tot);
-    s_local[tid] = lb;
-    __syncthreads();
-    if (s_fail) {
-        if (tid == 0) atomicExch(&P->status, kStatusDevice);
-        return;
-    }
     // stage the tile in LDS in digit order, then write each digit's run
     // contiguously; in pair mode the values follow through the same buffer
 #pragma unroll
@@ -554,15 +544,6 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(const uint64_t *__restrict
             if (pos[i] != 0xFFFFFFFFu) dstv[pos[i]] = s_vbuf[j];
         }
     }
-#ifdef FEC_SORT_TIMING
-    if (tid == 0) {
-        const uint64_t t_end = wall_clock64();
-        atomicAdd(&P->counters[0], (unsigned long long)(t_ticket - t_start));
-        atomicAdd(&P->counters[1], (unsigned long long)(t_lb - t_ticket));
-        atomicAdd(&P->counters[2], (unsigned long long)(t_end - t_lb));
-        atomicAdd(&P->counters[3], 1ull);
-    }
-#endif
 }
 
 // ------------------------------------------------------------- 5. gather
@@ -2235,7 +2216,8 @@ __global__ void k_finish(const Params *__restrict__ P, int32_t *__restrict__ k_o
 
 const char *stage_name(int s) {
     static const char *names[kNumStages] = {
-        "bbox",      "plan",      "keys",       "sort_pass",  "gather",      "tile_scan",
+        "bbox",      "plan",      "keys",       "sort_hist",  "sort_scan",   "sort_scatter",
+        "gather",    "tile_scan",
         "cells",     "colgrid",   "tile_list",  "hook_tile",  "hook_subtile", "link_edges",
         "hook_cells",
         "runs",      "hook_near", "compress_1", "giant",      "work_list",   "hook_far",
@@ -2255,8 +2237,7 @@ hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_siz
     uint64_t *keys1 = reinterpret_cast<uint64_t *>(w + L.keys1);
     uint32_t *vals0 = reinterpret_cast<uint32_t *>(w + L.vals0);
     uint32_t *vals1 = reinterpret_cast<uint32_t *>(w + L.vals1);
-    uint64_t *lb0 = reinterpret_cast<uint64_t *>(w + L.lb0);
-    uint64_t *lb1 = reinterpret_cast<uint64_t *>(w + L.lb1);
+    uint32_t *th = reinterpret_cast<uint32_t *>(w + L.th);
     float4 *spts = reinterpret_cast<float4 *>(w + L.spts);
     uint32_t *sorig = reinterpret_cast<uint32_t *>(w + L.sorig);
     uint32_t *cell_start = reinterpret_cast<uint32_t *>(w + L.cell_start);
@@ -2296,17 +2277,17 @@ hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_siz
     FEC_LAUNCH(kStBbox, k_bbox<<<nb_bbox, kBlock, 0, st>>>(xyz, n, partials));
     FEC_LAUNCH(kStPlan, k_plan<<<1, kBlock, 0, st>>>(partials, nb_bbox, P, n, d, min_size,
                                                       max_size, L.colgrid_cap, hook_tiles));
-    FEC_LAUNCH(kStKeys, k_keys<<<nb_stream, kBlock, 0, st>>>(xyz, P, keys0, vals0, lb0,
-                                                              ntiles * kRadix));
+    FEC_LAUNCH(kStKeys, k_keys<<<nb_stream, kBlock, 0, st>>>(xyz, P, keys0, vals0));
     for (int pass = 0; pass < max_passes; ++pass) {
         const uint64_t *src = (pass & 1) ? keys1 : keys0;
         uint64_t *dst = (pass & 1) ? keys0 : keys1;
         const uint32_t *srcv = (pass & 1) ? vals1 : vals0;
         uint32_t *dstv = (pass & 1) ? vals0 : vals1;
-        uint64_t *cur = (pass & 1) ? lb1 : lb0;
-        uint64_t *nxt = (pass & 1) ? lb0 : lb1;
-        FEC_LAUNCH(kStSort, k_sort_pass<<<(unsigned)ntiles, kBlock, 0, st>>>(
-                                src, dst, srcv, dstv, P, cur, nxt, pass, n, ntiles));
+        FEC_LAUNCH(kStSortHist,
+                   k_sort_hist<<<(unsigned)ntiles, kBlock, 0, st>>>(src, P, pass, n, ntiles, th));
+        FEC_LAUNCH(kStSortScan, k_sort_scan<<<kRadix, kBlock, 0, st>>>(P, pass, ntiles, th));
+        FEC_LAUNCH(kStSort, k_sort_scatter<<<(unsigned)ntiles, kBlock, 0, st>>>(
+                                src, dst, srcv, dstv, P, pass, n, ntiles, th));
     }
     FEC_LAUNCH(kStGather, k_gather<<<(unsigned)ntiles, kBlock, 0, st>>>(
                               xyz, keys0, keys1, vals0, vals1, colbits, P, spts, sorig,

@@ -20,10 +20,6 @@ constexpr int kCellBlocks = 4096;      // grid of the grid-stride per-cell kerne
 // kColGridPerPoint entries per point (else columns are binary-searched).
 constexpr int kColGridPerPoint = 8;
 
-// Look-back words of the radix passes: 2-bit flag + 62-bit count.
-constexpr uint64_t kLbAggregate = 1ull << 62;
-constexpr uint64_t kLbInclusive = 2ull << 62;
-constexpr uint64_t kLbValue = (1ull << 62) - 1;
 
 // Device-side status values (mirror the public FEC_* codes).
 constexpr int32_t kStatusOk = 0;
@@ -68,14 +64,13 @@ struct Params {
     int32_t kept;         // kept clusters
     int32_t max_cell;     // largest number of points in one cell
     unsigned long long counters[8];  // diagnostic event counts (counting builds only)
-    uint32_t ticket[kMaxPasses];
     uint32_t hist[kMaxPasses][kRadix];
 };
 
 // ---------------------------------------------------------------- workspace
 struct Layout {
     size_t params, partials, tile_cnt, tile_off;
-    size_t keys0, keys1, vals0, vals1, lb0, lb1;
+    size_t keys0, keys1, vals0, vals1, th;
     size_t spts, sorig, cell_start, cell_key, cpar, csize, ccanon;
     size_t col_key, col_cell, colgrid, colbits, heads, blkhead, gbits, work, edges;
     uint64_t edge_cap;
@@ -111,8 +106,7 @@ inline Layout make_layout(int64_t n) {
     L.keys1 = take(un * sizeof(uint64_t));
     L.vals0 = take(un * sizeof(uint32_t));
     L.vals1 = take(un * sizeof(uint32_t));
-    L.lb0 = take((size_t)L.ntiles * kRadix * sizeof(uint64_t));
-    L.lb1 = take((size_t)L.ntiles * kRadix * sizeof(uint64_t));
+    L.th = take((size_t)L.ntiles * kRadix * sizeof(uint32_t));
     L.spts = take(un * sizeof(float4));
     L.sorig = take(un * sizeof(uint32_t));
     L.cell_start = take((un + 1) * sizeof(uint32_t));
@@ -141,6 +135,8 @@ enum Stage : int {
     kStBbox = 0,
     kStPlan,
     kStKeys,
+    kStSortHist,
+    kStSortScan,
     kStSort,
     kStGather,
     kStTileScan,

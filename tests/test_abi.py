@@ -48,7 +48,7 @@ def test_workspace_bytes_linear(fec):
 
 def test_stage_names(fec):
     names = fec.stage_names()
-    assert "hook_near" in names and "sort_pass" in names and len(names) == len(set(names))
+    assert "hook_near" in names and "sort_scatter" in names and len(names) == len(set(names))
 
 
 def test_host_side_argument_checks(fec):
