@@ -88,20 +88,6 @@ int32_t fec_cluster_async(const float *xyz, int64_t n, float d, int32_t min_size
                           int32_t max_size, int32_t *labels_out, int32_t *k_out, void *workspace,
                           size_t workspace_bytes, void *stream);
 
-/*
- * Hooking strategy for later calls (process-wide; the computed labels are
- * the same either way):
- *   FEC_HOOK_CELLS  one thread per grid cell joins it to its neighbour cells
- *                   through a union-find in device memory (default);
- *   FEC_HOOK_TILES  where the cloud's (x, y) extent allows a dense column
- *                   index, blocks of columns are staged in on-chip memory
- *                   and joined there, with links between blocks afterwards.
- * Returns the previous mode, or FEC_EINVAL for an unknown mode.
- */
-#define FEC_HOOK_CELLS 0
-#define FEC_HOOK_TILES 1
-int32_t fec_set_hooking(int32_t mode);
-
 /* Stream used by fec_cluster (a hipStream_t; NULL = null stream).  Returns FEC_OK. */
 int32_t fec_set_stream(void *stream);
 
@@ -119,14 +105,10 @@ const char *fec_version(void);
  * out[0] n, out[1] finite points, out[2] occupied grid cells, out[3] occupied
  * grid columns, out[4] grid key bits, out[5] radix passes, out[6..8] grid
  * cells along x, y, z, out[9] largest points per cell, out[10] status,
- * out[11] cells left outside the largest component by the sampling phase and
- * out[12] that component's root cell (both when the (x, y) plane is too
- * large for a dense column index, else 0 and -1), out[13] occupied tiles,
- * out[14] sub-tiles of tiles over the on-chip capacity, out[15] sub-tiles
- * handled cell by cell, out[16] links between tiles (dense index only, else
- * 0), out[17..24] diagnostic event counts (zero unless the library was built
- * with FEC_COUNTERS defined).
- * Writes min(max_out, 25) values; returns that count or a negative status.
+ * out[11] cells left outside the largest component after the near shell,
+ * out[12] that component's root cell, out[13..20] diagnostic event counts
+ * (zero unless the library was built with FEC_COUNTERS defined).
+ * Writes min(max_out, 21) values; returns that count or a negative status.
  */
 int32_t fec_workspace_stats(const void *workspace, void *stream, int64_t *out, int32_t max_out);
 

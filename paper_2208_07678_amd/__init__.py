@@ -46,6 +46,10 @@ def _load():
         raise ImportError(
             "paper_2208_07678_amd: HIP library %s is missing; build it with "
             "'python -m paper_2208_07678_amd.build'" % lib_path)
+    # torch ships its own HIP runtime under the same soname; loading it first
+    # makes this library bind to that one, so the process has one runtime
+    # (two would each try to own the device)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(lib_path)
     i32, i64, f32, vp, u64 = (ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_void_p,
                               ctypes.c_uint64)
@@ -54,7 +58,6 @@ def _load():
         "fec_workspace_bytes": ([i64], ctypes.c_size_t),
         "fec_cluster_async": ([vp, i64, f32, i32, i32, vp, vp, vp, ctypes.c_size_t, vp], i32),
         "fec_set_stream": ([vp], i32),
-        "fec_set_hooking": ([i32], i32),
         "fec_release": ([], None),
         "fec_last_error": ([], ctypes.c_char_p),
         "fec_version": ([], ctypes.c_char_p),
@@ -74,16 +77,14 @@ def _load():
 
 
 EXPORTED = [
-    "fec_cluster", "fec_workspace_bytes", "fec_cluster_async", "fec_set_stream",
-    "fec_set_hooking", "fec_release",
+    "fec_cluster", "fec_workspace_bytes", "fec_cluster_async", "fec_set_stream", "fec_release",
     "fec_last_error", "fec_version", "fec_workspace_stats", "fec_profile_enable",
     "fec_profile_read", "fec_profile_reset", "fec_stage_count", "fec_stage_name",
 ]
 
 STATS_FIELDS = ["n", "finite_points", "cells", "columns", "key_bits", "radix_passes",
                 "grid_x", "grid_y", "grid_z", "max_points_per_cell", "status",
-                "work_cells", "giant_root", "tiles", "subtiles",
-                "cell_pass_subtiles", "tile_edges"] + ["counter%d" % i for i in range(8)]
+                "work_cells", "giant_root"] + ["counter%d" % i for i in range(8)]
 
 
 class FecError(RuntimeError):
@@ -94,19 +95,6 @@ class FecError(RuntimeError):
 
 def _raise(code: int):
     raise FecError(code, (_load().fec_last_error() or b"").decode())
-
-
-HOOK_CELLS = 0
-HOOK_TILES = 1
-
-
-def set_hooking(mode: int) -> int:
-    """Selects per-cell (HOOK_CELLS) or tile (HOOK_TILES) hooking for later
-    calls; returns the previous mode."""
-    rc = _load().fec_set_hooking(int(mode))
-    if rc < 0:
-        _raise(rc)
-    return rc
 
 
 def version() -> str:

@@ -114,8 +114,6 @@ struct Cached {
     hipStream_t stream = nullptr;
 } g_cache;
 
-std::atomic<int32_t> g_hooking{FEC_HOOK_CELLS};
-
 }  // namespace
 
 extern "C" {
@@ -156,18 +154,10 @@ int32_t fec_cluster_async(const float *xyz, int64_t n, float d, int32_t min_size
     {
         std::lock_guard<std::mutex> lock(g_mu);
         e = fec::launch_pipeline(xyz, n, d, min_size, max_size, labels_out, k_out, workspace, L,
-                                 st, g_timer.mask ? &g_timer : nullptr, g_hooking.load());
+                                 st, g_timer.mask ? &g_timer : nullptr);
     }
     if (e != hipSuccess) return fail(FEC_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return ok();
-}
-
-int32_t fec_set_hooking(int32_t mode) {
-    if (mode != FEC_HOOK_CELLS && mode != FEC_HOOK_TILES)
-        return fail(FEC_EINVAL, "unknown hooking mode %d", mode);
-    const int32_t prev = g_hooking.exchange(mode);
-    ok();
-    return prev;
 }
 
 int32_t fec_set_stream(void *stream) {
@@ -224,14 +214,13 @@ int32_t fec_workspace_stats(const void *workspace, void *stream, int64_t *out, i
     if (hipMemcpyAsync(&P, workspace, sizeof P, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return fail(FEC_EDEVICE, "reading the workspace failed");
-    const int64_t v[25] = {P.n,  P.nvalid, P.M,  P.Mcol,     P.key_bits, P.npasses, P.NX,
+    const int64_t v[21] = {P.n,  P.nvalid, P.M,  P.Mcol,     P.key_bits, P.npasses, P.NX,
                            P.NY, P.NZ,     P.max_cell, P.status, P.nwork,   P.giant,
-                           P.ntile, P.nsub, P.nglob, P.nedges,
                            (int64_t)P.counters[0], (int64_t)P.counters[1],
                            (int64_t)P.counters[2], (int64_t)P.counters[3],
                            (int64_t)P.counters[4], (int64_t)P.counters[5],
                            (int64_t)P.counters[6], (int64_t)P.counters[7]};
-    const int32_t c = max_out < 25 ? max_out : 25;
+    const int32_t c = max_out < 21 ? max_out : 21;
     for (int32_t i = 0; i < c; ++i) out[i] = v[i];
     ok();
     return c;

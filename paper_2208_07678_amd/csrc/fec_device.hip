@@ -95,32 +95,6 @@ __device__ __forceinline__ bool finite3(float x, float y, float z) {
     return isfinite(x) && isfinite(y) && isfinite(z);
 }
 
-// Lower bound of Eq. (1)'s binary32 value over all point pairs of two
-// boxes: the per-axis gaps are rounded differences of box faces and the sum
-// is taken in the predicate's order, and every step is monotone in its
-// operands, so no pair of points in the boxes evaluates below it.  A bound
-// not below d2 proves that no pair is joined.
-__device__ __forceinline__ float box_gap2(float4 alo, float4 ahi, float4 blo, float4 bhi) {
-#pragma clang fp contract(off)
-    const float gx = fmaxf(fmaxf(blo.x - ahi.x, alo.x - bhi.x), 0.0f);
-    const float gy = fmaxf(fmaxf(blo.y - ahi.y, alo.y - bhi.y), 0.0f);
-    const float gz = fmaxf(fmaxf(blo.z - ahi.z, alo.z - bhi.z), 0.0f);
-    float s = gx * gx + gy * gy;
-    s = s + gz * gz;
-    return s;
-}
-
-// Same bound for one point against a box.
-__device__ __forceinline__ float point_gap2(float x, float y, float z, float4 blo, float4 bhi) {
-#pragma clang fp contract(off)
-    const float gx = fmaxf(fmaxf(blo.x - x, x - bhi.x), 0.0f);
-    const float gy = fmaxf(fmaxf(blo.y - y, y - bhi.y), 0.0f);
-    const float gz = fmaxf(fmaxf(blo.z - z, z - bhi.z), 0.0f);
-    float s = gx * gx + gy * gy;
-    s = s + gz * gz;
-    return s;
-}
-
 // Block-wide exclusive scan of one value per thread (kBlock threads).
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_tmp, uint32_t &total) {
     const int lane = __lane_id();
@@ -195,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_bbox(const float *__restrict__ xyz, 
 __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ partials, int nparts,
                                                  Params *__restrict__ P, int64_t n, float d,
                                                  int32_t min_size, int32_t max_size,
-                                                 uint64_t colgrid_cap, int hook_tiles) {
+                                                 uint64_t colgrid_cap) {
     float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY;
     float hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
     uint64_t cnt = 0;
@@ -263,18 +237,12 @@ __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ parti
     P->ox = o3[0]; P->oy = o3[1]; P->oz = o3[2];
     P->NX = N3[0]; P->NY = N3[1]; P->NZ = N3[2];
     P->NYp = (N3[1] + 31) / 32 * 32;
-    P->ntile = 0;
-    P->nsub = 0;
-    P->nglob = 0;
-    for (int i = 0; i < 16; ++i) (&P->ticket_tile[0][0])[i] = 0;
-    P->nedges = 0;
     P->bx = bits_for(N3[0]);
     P->by = bits_for(N3[1]);
     P->bz = bits_for(N3[2]);
     P->giant = -1;
     P->nwork = 0;
     P->dense_cols = ((double)N3[0] * (double)P->NYp <= (double)colgrid_cap) ? 1 : 0;
-    P->use_tiles = (P->dense_cols && hook_tiles) ? 1 : 0;
     const int B = P->bx + P->by + P->bz;
     const int kb = B + (((int64_t)c < n) ? 1 : 0);
     int ib = bits_for(n);
@@ -758,10 +726,9 @@ __device__ __forceinline__ Grid grid_of(const Params *P) {
     return g;
 }
 
-// Dense column index, valid where the occupancy bit is set (bits are
-// cleared every call, the index itself is not): colgrid[cx * NYp + cy] is
-// the column id of (cx, cy) when hooking by tiles (its cells are
-// col_cell[id] .. col_cell[id + 1]), else its first cell.  Also writes the end markers of the cell and column
+// Dense column index: colgrid[cx * NYp + cy] = first cell of column
+// (cx, cy), valid where the occupancy bit is set (bits are cleared every
+// call, the index itself is not).  Also writes the end markers of the cell and column
 // tables.
 __global__ __launch_bounds__(kBlock) void k_colgrid(const uint64_t *__restrict__ col_key,
                                                     uint32_t *__restrict__ col_cell,
@@ -777,7 +744,6 @@ __global__ __launch_bounds__(kBlock) void k_colgrid(const uint64_t *__restrict__
     }
     if (!P->dense_cols) return;
     const Grid g = grid_of(P);
-    const int tiles = P->use_tiles;
     const int lane = __lane_id();
     for (int64_t c0 = (int64_t)blockIdx.x * kBlock; c0 < Mcol; c0 += (int64_t)gridDim.x * kBlock) {
         const int64_t c = c0 + threadIdx.x;
@@ -787,7 +753,7 @@ __global__ __launch_bounds__(kBlock) void k_colgrid(const uint64_t *__restrict__
             int64_t cx, cy;
             g.col_xy(col_key[c], cx, cy);
             idx = (uint64_t)(cx * g.NYp + cy);
-            colgrid[idx] = tiles ? (uint32_t)c : col_cell[c];
+            colgrid[idx] = col_cell[c];
         }
         // columns are sorted, so a wave's bits fall into few words: one
         // atomic OR per distinct word
@@ -818,7 +784,7 @@ __device__ __forceinline__ bool find_column(const Grid &g, int64_t cx, int64_t c
     if (dense) {
         const uint64_t idx = (uint64_t)(cx * g.NYp + cy);
         if (!((colbits[idx >> 5] >> (idx & 31)) & 1u)) return false;
-        first = colgrid[idx];  // per-cell hooking: first cell
+        first = colgrid[idx];
         return true;
     }
     const uint64_t want = g.col_key((uint64_t)cx, (uint64_t)cy);
@@ -935,7 +901,7 @@ __global__ __launch_bounds__(kBlock) void k_runs1(const float4 *__restrict__ spt
                                                   uint8_t *__restrict__ heads,
                                                   int32_t *__restrict__ blkhead,
                                                   const Params *__restrict__ P) {
-    if (P->status != kStatusOk || P->use_tiles) return;
+    if (P->status != kStatusOk) return;
     const int64_t M = P->M;
     const int64_t base = (int64_t)blockIdx.x * kTile;
     if (base >= M) return;
@@ -976,7 +942,7 @@ __global__ __launch_bounds__(kBlock) void k_runs2(const uint8_t *__restrict__ he
                                                   const int32_t *__restrict__ blkhead,
                                                   int32_t *__restrict__ cpar,
                                                   const Params *__restrict__ P) {
-    if (P->status != kStatusOk || P->use_tiles) return;
+    if (P->status != kStatusOk) return;
     const int64_t M = P->M;
     const int64_t base = (int64_t)blockIdx.x * kTile;
     if (base >= M) return;
@@ -1049,7 +1015,7 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
                                                       const uint32_t *__restrict__ colgrid,
                                                       const uint32_t *__restrict__ colbits,
                                                       int32_t *cpar, const Params *__restrict__ P) {
-    if (P->status != kStatusOk || P->use_tiles) return;
+    if (P->status != kStatusOk) return;
     const int64_t M = P->M, Mcol = P->Mcol;
     const int dense = P->dense_cols;
     const float d2 = P->d2;
@@ -1175,9 +1141,8 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
 // Every cell points at its root afterwards.  Runs after all joins (data is
 // coherent at the kernel boundary); each slot is written once, with the
 // root, so concurrent finds only ever see ancestors.
-__global__ __launch_bounds__(kBlock) void k_compress(int32_t *cpar, const Params *__restrict__ P,
-                                                     int sparse_only) {
-    if (P->status != kStatusOk || (sparse_only && P->use_tiles)) return;
+__global__ __launch_bounds__(kBlock) void k_compress(int32_t *cpar, const Params *__restrict__ P) {
+    if (P->status != kStatusOk) return;
     const int64_t M = P->M;
     for (int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x; x < M;
          x += (int64_t)gridDim.x * kBlock) {
@@ -1191,7 +1156,7 @@ constexpr int kGiantSlots = 8192;
 
 __global__ __launch_bounds__(1024) void k_giant(const int32_t *__restrict__ cpar,
                                                 Params *__restrict__ P) {
-    if (P->status != kStatusOk || P->use_tiles) return;
+    if (P->status != kStatusOk) return;
     __shared__ int32_t t_key[kGiantSlots];
     __shared__ uint32_t t_cnt[kGiantSlots];
     __shared__ uint64_t s_best[1024 / 64];
@@ -1248,7 +1213,7 @@ __global__ __launch_bounds__(kBlock) void k_nongiant(const int32_t *__restrict__
                                                      uint64_t *__restrict__ gbits,
                                                      uint32_t *__restrict__ work,
                                                      Params *__restrict__ P) {
-    if (P->status != kStatusOk || P->use_tiles) return;
+    if (P->status != kStatusOk) return;
     __shared__ uint32_t s_wcnt[kBlock / 64];
     __shared__ uint32_t s_base;
     const int64_t M = P->M;
@@ -1318,7 +1283,7 @@ __global__ __launch_bounds__(kBlock) void k_hook_far(const float4 *__restrict__ 
                                                       const uint64_t *__restrict__ gbits,
                                                       const uint32_t *__restrict__ work,
                                                       int32_t *cpar, const Params *__restrict__ P) {
-    if (P->status != kStatusOk || P->use_tiles) return;
+    if (P->status != kStatusOk) return;
     const int64_t M = P->M, Mcol = P->Mcol;
     const uint32_t nwork = P->nwork;
     const int dense = P->dense_cols;
@@ -1430,641 +1395,6 @@ __global__ __launch_bounds__(kBlock) void k_hook_far(const float4 *__restrict__ 
                         if (dz > 2) break;
                         if (dz < -2 || (near_col && dz >= -1 && dz <= 1)) continue;
                         if (fwd || is_giant(gbits, B)) pair(B, cpar[B]);
-                    }
-                }
-            }
-        }
-    }
-}
-
-// ------------------------------------------------------------- 8b. tiles
-// Dense-index mode.  The (cx, cy) plane is cut into tiles of kTX rows (x)
-// by kTW = 32 columns (y): one occupancy word per tile row.  A tile's own
-// cells (its "core") and the cells its forward stencil reaches outside it
-// (its "halo": two more rows along +x and two more columns on each side)
-// are staged in LDS together with their points.  Every forward cell pair
-// whose first cell is in the core is examined there, against a union-find
-// in LDS.  Each cell is in the core of exactly one tile, so each cell pair
-// of the 5x5x5 stencil is examined by exactly one tile.
-//
-// The result goes to the global union-find: a core cell whose LDS root is
-// another core cell is hooked under it, and a halo cell that joined a core
-// component (the halo cell is in another tile's core) is linked to it.
-// Both use compare-and-swap on roots only, so tiles run in any order.
-//
-// Tiles over the LDS capacity are re-run as sub-tiles of kSubRows core rows
-// (each with its own halo), and sub-tiles still over it go through a
-// per-cell pass over global memory.
-constexpr int kTX = 8;                  // core rows per tile
-constexpr int kSubRows = 2;             // core rows per sub-tile of an oversized tile
-constexpr int kTW = 32;                 // core columns per tile
-constexpr int kHW = kTW + 4;            // staged columns: 2 + 32 + 2
-constexpr int kHR = kTX + 2;            // staged rows
-constexpr int kSlots = kHR * kHW;       // staged columns of a tile
-constexpr int kSegMax = 3 * kTX + 2;    // staged cell ranges (see k_hook_tile)
-constexpr int kTileCapP = 2048;         // staged points per tile (LDS)
-constexpr int kTileCapC = 704;          // staged cells per tile (LDS)
-constexpr int kTileBlocks = 2048;       // blocks of the tile kernels (work is fetched by ticket)
-constexpr int kJobChunk = 4;            // tiles per ticket
-static_assert(kTileBlocks % 8 == 0, "every ticket counter has blocks");
-static_assert(kTX % kSubRows == 0, "sub-tiles split a tile evenly");
-static_assert(kTX <= 16, "tile descriptors keep nrows - 1 in 4 bits");
-
-// Tile descriptor: first core row cx0, column word ty, core rows.
-__device__ __forceinline__ uint64_t tile_desc(int64_t cx0, int64_t ty, int nrows) {
-    return ((uint64_t)cx0 << 32) | ((uint64_t)ty << 4) | (uint64_t)(nrows - 1);
-}
-__device__ __forceinline__ void tile_undesc(uint64_t t, int64_t &cx0, int64_t &ty, int &nrows) {
-    cx0 = (int64_t)(t >> 32);
-    ty = (int64_t)((t >> 4) & 0x0FFFFFFFu);
-    nrows = (int)(t & 15u) + 1;
-}
-
-// Appends v to list[*counter], or flags a device error beyond cap.
-__device__ __forceinline__ void list_push(uint64_t *list, uint32_t *counter, uint32_t cap,
-                                          uint64_t v, Params *P) {
-    const uint32_t i = atomicAdd(counter, 1u);
-    if (i < cap) list[i] = v;
-    else atomicExch(&P->status, kStatusDevice);
-}
-
-// Occupied tiles (any core row word non-zero), appended per block.
-__global__ __launch_bounds__(kBlock) void k_tile_list(const uint32_t *__restrict__ colbits,
-                                                      uint64_t *__restrict__ tiles,
-                                                      uint32_t cap, Params *__restrict__ P) {
-    if (P->status != kStatusOk || !P->use_tiles) return;
-    const int64_t NX = P->NX, W = P->NYp / kTW;
-    const int64_t ntx = (NX + kTX - 1) / kTX;
-    const int64_t T = ntx * W;
-    __shared__ uint32_t s_cnt[kBlock / 64];
-    __shared__ uint32_t s_base;
-    const int lane = __lane_id(), wave = threadIdx.x >> 6;
-    for (int64_t t0 = (int64_t)blockIdx.x * kBlock; t0 < T; t0 += (int64_t)gridDim.x * kBlock) {
-        const int64_t t = t0 + threadIdx.x;
-        int64_t tx = 0, ty = 0;
-        bool occ = false;
-        if (t < T) {
-            tx = t / W;
-            ty = t - tx * W;
-            uint32_t any = 0;
-#pragma unroll
-            for (int r = 0; r < kTX; ++r) {
-                const int64_t cx = tx * kTX + r;
-                if (cx < NX) any |= colbits[cx * W + ty];
-            }
-            occ = any != 0;
-        }
-        const uint64_t m = __ballot(occ);
-        if (lane == 0) s_cnt[wave] = (uint32_t)__popcll(m);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t tot = 0;
-            for (int i = 0; i < kBlock / 64; ++i) {
-                const uint32_t c = s_cnt[i];
-                s_cnt[i] = tot;
-                tot += c;
-            }
-            s_base = tot ? atomicAdd(&P->ntile, tot) : 0u;
-        }
-        __syncthreads();
-        if (occ) {
-            const uint32_t i = s_base + s_cnt[wave] + (uint32_t)__popcll(m & lanemask_lt());
-            const int64_t cx0 = tx * kTX;
-            const int nr = (int)(NX - cx0 < kTX ? NX - cx0 : kTX);
-            if (i < cap) tiles[i] = tile_desc(cx0, ty, nr);
-            else atomicExch(&P->status, kStatusDevice);
-        }
-        __syncthreads();
-    }
-}
-
-// LDS union-find of one tile: relaxed workgroup-scope accesses (the LDS is
-// coherent within the block); parents only ever move to ancestors.
-__device__ __forceinline__ uint32_t lds_ld(const uint32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ void lds_st(uint32_t *p, uint32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ uint32_t lds_find(uint32_t *par, uint32_t x) {
-    uint32_t p = lds_ld(par + x);
-    while (p != x) {
-        const uint32_t gp = lds_ld(par + p);
-        if (gp != p) lds_st(par + x, gp);  // path splitting
-        x = p;
-        p = gp;
-    }
-    return x;
-}
-__device__ __forceinline__ void lds_union(uint32_t *par, uint32_t a, uint32_t b) {
-    while (a != b) {
-        const uint32_t hi = a > b ? a : b, lo = a > b ? b : a;
-        uint32_t seen = hi;
-        if (__hip_atomic_compare_exchange_strong(par + hi, &seen, lo, __ATOMIC_RELAXED,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
-            return;
-        if (hi == a) a = lds_find(par, seen);
-        else b = lds_find(par, seen);
-    }
-}
-
-// Any joined pair between the staged points [a0, a1) and [b0, b1) (xyz
-// triples); points of the first range that are out of reach of the second
-// range's box are skipped.
-__device__ __forceinline__ bool lds_any_joined(const float *pts, uint32_t a0, uint32_t a1,
-                                               uint32_t b0, uint32_t b1, float4 blo, float4 bhi,
-                                               float d2, uint64_t &evals) {
-    for (uint32_t a = a0; a < a1; ++a) {
-        const float ax = pts[3 * a], ay = pts[3 * a + 1], az = pts[3 * a + 2];
-        if (!(point_gap2(ax, ay, az, blo, bhi) < d2)) continue;
-        for (uint32_t b = b0; b < b1; ++b) {
-#ifdef FEC_COUNTERS
-            ++evals;
-#endif
-            const float4 pb = make_float4(pts[3 * b], pts[3 * b + 1], pts[3 * b + 2], 0.0f);
-            if (joined(ax, ay, az, pb, d2)) return true;
-        }
-    }
-    return false;
-}
-
-// Column offsets (dx, dy) of the forward half of the 5x5 neighbourhood, in
-// the order (0,1), (0,2), then dx = 1, 2 with dy = -2 .. 2 (computed, not
-// tabulated: a table indexed per lane would be read from global memory).
-__device__ __forceinline__ void fwd_col(int q, int &dx, int &dy) {
-    if (q < 2) {
-        dx = 0;
-        dy = q + 1;
-    } else {
-        dx = q < 7 ? 1 : 2;
-        dy = (q < 7 ? q - 2 : q - 7) - 2;
-    }
-}
-// The near-shell columns: (0,1), (1,-1), (1,0), (1,1) for k = 0 .. 3.
-__device__ __forceinline__ void near_col(int k, int &dx, int &dy) {
-    dx = k == 0 ? 0 : 1;
-    dy = k == 0 ? 1 : k - 2;
-}
-
-template <int kCapP, int kCapC>
-__global__ __launch_bounds__(kBlock) void k_hook_tile(
-    const float4 *__restrict__ spts, const uint32_t *__restrict__ cell_start,
-    const uint64_t *__restrict__ cell_key, const uint32_t *__restrict__ col_cell,
-    const uint32_t *__restrict__ colgrid, const uint32_t *__restrict__ colbits,
-    const uint64_t *__restrict__ jobs, int level, uint64_t *__restrict__ spill,
-    uint32_t spill_cap, uint64_t *__restrict__ edges, uint32_t edge_cap, int32_t *cpar,
-    Params *__restrict__ P) {
-    static_assert(kCapP <= 65535 && kCapC <= 65535, "LDS offsets are 16-bit");
-    if (P->status != kStatusOk || !P->use_tiles) return;
-    const uint32_t njobs = level == 0 ? P->ntile : P->nsub;
-    uint32_t *spill_count = level == 0 ? &P->nsub : &P->nglob;
-    const Grid g = grid_of(P);
-    const int64_t W = g.NYp / kTW;
-    const float d2 = P->d2;
-    const int tid = threadIdx.x;
-
-    __shared__ float s_pts[3 * kCapP];    // staged points, x y z
-    // per staged cell: box of its points; lo.w = z index, hi.w = first
-    // staged point (so the points of cell l are [hi[l].w, hi[l+1].w))
-    __shared__ float4 s_lo[kCapC];
-    __shared__ float4 s_hi[kCapC + 1];
-    __shared__ uint32_t s_par[kCapC];
-    __shared__ uint16_t s_slot[kCapC];    // staged column of cell l: row * kHW + column
-    __shared__ uint16_t s_cfirst[kSlots];  // staged cells of a column: [s_cfirst, s_cend)
-    __shared__ uint16_t s_cend[kSlots];
-    // staged ranges: global first cell, cells, global first point, points;
-    // staged offsets of cells and points (prefix sums in staging order)
-    __shared__ uint32_t s_sg[kSegMax], s_sn[kSegMax], s_spg[kSegMax], s_spn[kSegMax];
-    __shared__ uint32_t s_sl[kSegMax + 1], s_spl[kSegMax + 1];
-
-#ifdef FEC_COUNTERS
-    uint64_t t_mark = 0;
-    // level 0 only: wall time of the phases of a tile (thread 0, 10 ns
-    // ticks) in counters 0-3; pair tests and point-pair evaluations of the
-    // near and far phases in counters 4-7
-    uint64_t c_tests[2] = {0, 0}, c_evals[2] = {0, 0}, c_maxev = 0;
-#define TILE_PHASE(i)                                                          \
-    do {                                                                       \
-        if (tid == 0 && level == 0) {                                          \
-            const uint64_t t_now = wall_clock64();                             \
-            FEC_COUNT(P, (i), t_now - t_mark);                                 \
-            t_mark = t_now;                                                    \
-        }                                                                      \
-    } while (0)
-#else
-#define TILE_PHASE(i) ((void)0)
-#endif
-    // Jobs are taken in chunks of kJobChunk from one of eight ticket
-    // counters (chosen by block id, so spread over the XCDs); counter c
-    // deals chunks c, c + 8, c + 16, ...  Thread 0 asks for the next chunk
-    // while the current one runs.
-    __shared__ uint32_t s_chunk;
-    uint32_t *ticket = &P->ticket_tile[level][blockIdx.x & 7];
-    if (tid == 0) s_chunk = atomicAdd(ticket, 1u);
-    for (;;) {
-        __syncthreads();
-        const uint32_t chunk = s_chunk * 8 + (blockIdx.x & 7);
-        if ((uint64_t)chunk * kJobChunk >= njobs) break;
-        uint32_t next_chunk = 0;
-        if (tid == 0) next_chunk = atomicAdd(ticket, 1u);
-        const uint32_t job_end =
-            (uint64_t)chunk * kJobChunk + kJobChunk < njobs ? chunk * kJobChunk + kJobChunk : njobs;
-    for (uint32_t job = chunk * kJobChunk; job < job_end; ++job) {
-#ifdef FEC_COUNTERS
-        if (tid == 0) t_mark = wall_clock64();
-#endif
-        int64_t cx0, ty;
-        int nrows;
-        tile_undesc(jobs[job], cx0, ty, nrows);
-        const int nl = nrows + 2;          // staged rows
-        const int nseg = 3 * nrows + 2;
-        const int64_t cy0 = ty * kTW - 2;  // y of staged column 0
-
-        // 1. Staged rows.  In row r the occupied columns are consecutive
-        // column ids, so the row's cells and points are contiguous ranges;
-        // they are cut into left halo, centre and right halo.  Staging
-        // order: the centres of the core rows (the core, in global cell
-        // order), then the sides of the core rows, then the two halo rows.
-        for (int i = tid; i < kSlots; i += kBlock) {
-            s_cfirst[i] = 0;
-            s_cend[i] = 0;
-        }
-        if (tid < nl) {
-            const int r = tid;
-            const int64_t cx = cx0 + r;
-            uint64_t m = 0;
-            if (cx < g.NX) {
-                const int64_t wb = cx * W + ty;
-                const uint32_t wl = ty > 0 ? colbits[wb - 1] : 0u;
-                const uint32_t wc = colbits[wb];
-                const uint32_t wr = ty + 1 < W ? colbits[wb + 1] : 0u;
-                m = (uint64_t)(wl >> 30) | ((uint64_t)wc << 2) | ((uint64_t)(wr & 3u) << 34);
-            }
-            uint32_t cb[4] = {0, 0, 0, 0}, pb[4] = {0, 0, 0, 0};
-            if (m) {
-                const int j0 = __ffsll((unsigned long long)m) - 1;
-                const uint32_t id0 = colgrid[(uint64_t)(cx * g.NYp + cy0 + j0)];
-                const int jb[4] = {0, 2, 2 + kTW, kHW};
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const uint64_t below = m & ((1ull << jb[k]) - 1);
-                    cb[k] = col_cell[id0 + (uint32_t)__popcll(below)];
-                }
-#pragma unroll
-                for (int k = 0; k < 4; ++k) pb[k] = cell_start[cb[k]];
-            }
-            auto put = [&](int k, int a, int b) {
-                s_sg[k] = cb[a];
-                s_sn[k] = cb[b] - cb[a];
-                s_spg[k] = pb[a];
-                s_spn[k] = pb[b] - pb[a];
-            };
-            if (r < nrows) {
-                put(r, 1, 2);
-                put(nrows + 2 * r, 0, 1);
-                put(nrows + 2 * r + 1, 2, 3);
-            } else {
-                put(3 * nrows + (r - nrows), 0, 3);
-            }
-        }
-        __syncthreads();
-        if (tid == 0) {
-            uint32_t l = 0, p = 0;
-            for (int k = 0; k < nseg; ++k) {
-                s_sl[k] = l;
-                s_spl[k] = p;
-                l += s_sn[k];
-                p += s_spn[k];
-            }
-            s_sl[nseg] = l;
-            s_spl[nseg] = p;
-        }
-        __syncthreads();
-        const uint32_t L = s_sl[nseg], Pn = s_spl[nseg], Lc = s_sl[nrows];
-        const bool fits = L <= (uint32_t)kCapC && Pn <= (uint32_t)kCapP;
-        if (!fits) {
-            // hand the core rows on: sub-tiles, then the per-cell pass
-            if (tid == 0) {
-                if (level == 0) {
-                    for (int r = 0; r < nrows; r += kSubRows) {
-                        uint32_t core = 0;
-                        for (int q = r; q < r + kSubRows && q < nrows; ++q) core += s_sn[q];
-                        if (core) {
-                            const int nr = nrows - r < kSubRows ? nrows - r : kSubRows;
-                            list_push(spill, spill_count, spill_cap, tile_desc(cx0 + r, ty, nr), P);
-                        }
-                    }
-                } else {
-                    list_push(spill, spill_count, spill_cap, jobs[job], P);
-                }
-            }
-        } else if (Lc > 0) {
-            // 2. Stage cells and points.
-            for (uint32_t l = tid; l < L; l += kBlock) {
-                int lo = 0, hi = nseg - 1;  // last range starting at or before l
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_sl[mid] <= l) lo = mid;
-                    else hi = mid - 1;
-                }
-                const uint32_t gid = s_sg[lo] + (l - s_sl[lo]);
-                const uint64_t key = cell_key[gid];
-                const uint32_t st = cell_start[gid];
-                int64_t cx, cy;
-                g.col_xy(key >> g.bz, cx, cy);
-                s_lo[l].w = __int_as_float((int32_t)(key & g.zmask));
-                s_hi[l].w = __uint_as_float(s_spl[lo] + (st - s_spg[lo]));
-                s_par[l] = l;
-                s_slot[l] = (uint16_t)((cx - cx0) * kHW + (cy - cy0));
-            }
-            if (tid == 0) s_hi[L].w = __uint_as_float(Pn);
-            for (uint32_t p = tid; p < Pn; p += kBlock) {
-                int lo = 0, hi = nseg - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_spl[mid] <= p) lo = mid;
-                    else hi = mid - 1;
-                }
-                const float4 q = spts[s_spg[lo] + (p - s_spl[lo])];
-                s_pts[3 * p] = q.x;
-                s_pts[3 * p + 1] = q.y;
-                s_pts[3 * p + 2] = q.z;
-            }
-            __syncthreads();
-            // column map and cell boxes
-            for (uint32_t l = tid; l < L; l += kBlock) {
-                const uint32_t sl = s_slot[l];
-                if (l == 0 || s_slot[l - 1] != sl) s_cfirst[sl] = (uint16_t)l;
-                if (l + 1 == L || s_slot[l + 1] != sl) s_cend[sl] = (uint16_t)(l + 1);
-                const uint32_t p0 = __float_as_uint(s_hi[l].w), p1 = __float_as_uint(s_hi[l + 1].w);
-                float x0 = s_pts[3 * p0], y0 = s_pts[3 * p0 + 1], z0 = s_pts[3 * p0 + 2];
-                float x1 = x0, y1 = y0, z1 = z0;
-                for (uint32_t p = p0 + 1; p < p1; ++p) {
-                    const float x = s_pts[3 * p], y = s_pts[3 * p + 1], z = s_pts[3 * p + 2];
-                    x0 = fminf(x0, x); y0 = fminf(y0, y); z0 = fminf(z0, z);
-                    x1 = fmaxf(x1, x); y1 = fmaxf(y1, y); z1 = fmaxf(z1, z);
-                }
-                s_lo[l].x = x0; s_lo[l].y = y0; s_lo[l].z = z0;
-                s_hi[l].x = x1; s_hi[l].y = y1; s_hi[l].z = z1;
-            }
-            __syncthreads();
-            TILE_PHASE(0);
-
-#ifdef FEC_COUNTERS
-            int phase = 0;
-#endif
-            auto try_pair = [&](uint32_t A, uint32_t B) {
-                const uint32_t ra = lds_find(s_par, A), rb = lds_find(s_par, B);
-                if (ra == rb) return;
-                const float4 alo = s_lo[A], ahi = s_hi[A], blo = s_lo[B], bhi = s_hi[B];
-                if (!(box_gap2(alo, ahi, blo, bhi) < d2)) return;
-                uint64_t ev = 0;
-                const bool j =
-                    lds_any_joined(s_pts, __float_as_uint(ahi.w), __float_as_uint(s_hi[A + 1].w),
-                                   __float_as_uint(bhi.w), __float_as_uint(s_hi[B + 1].w), blo,
-                                   bhi, d2, ev);
-#ifdef FEC_COUNTERS
-                c_tests[phase] += 1;
-                c_evals[phase] += ev;
-                c_maxev = ev > c_maxev ? ev : c_maxev;
-#endif
-                if (j)
-                    lds_union(s_par, ra, rb);
-            };
-            auto z_of = [&](uint32_t l) { return __float_as_int(s_lo[l].w); };
-            // item index -> (offset, cell), offset-major: o = it / Lc as
-            // (it * ceil(2^32 / Lc)) >> 32, exact for it < 2^32 / Lc (the
-            // factor is 2^32 itself for Lc = 1, hence 64-bit)
-            const uint64_t magic = (0x100000000ull + Lc - 1) / Lc;
-            // 3. Near shell: own column dz = +1, and the four near columns
-            // with |dz| <= 1.
-            for (uint32_t it = tid; it < 5 * Lc; it += kBlock) {
-                const uint32_t o = (uint32_t)(((uint64_t)it * magic) >> 32), A = it - o * Lc;
-                const uint32_t sA = s_slot[A];
-                const int32_t zA = z_of(A);
-                if (o == 0) {
-                    const uint32_t B = A + 1;
-                    if (B < L && s_slot[B] == sA && z_of(B) == zA + 1) try_pair(A, B);
-                } else {
-                    int dx, dy;
-                    near_col((int)o - 1, dx, dy);
-                    const uint32_t ns = sA + dx * kHW + dy;
-                    const uint32_t e = s_cend[ns];
-                    for (uint32_t B = s_cfirst[ns]; B < e; ++B) {
-                        const int32_t dz = z_of(B) - zA;
-                        if (dz > 1) break;
-                        if (dz >= -1) try_pair(A, B);
-                    }
-                }
-            }
-            __syncthreads();
-            TILE_PHASE(1);
-#ifdef FEC_COUNTERS
-            phase = 1;
-#endif
-            // 4. Far shell: own column dz = +2, the near columns with
-            // |dz| = 2 and the other eight columns with |dz| <= 2.
-            for (uint32_t it = tid; it < 13 * Lc; it += kBlock) {
-                const uint32_t o = (uint32_t)(((uint64_t)it * magic) >> 32), A = it - o * Lc;
-                const uint32_t sA = s_slot[A];
-                const int32_t zA = z_of(A);
-                if (o == 0) {
-                    for (uint32_t B = A + 1; B < L && B <= A + 2 && s_slot[B] == sA; ++B) {
-                        const int32_t dz = z_of(B) - zA;
-                        if (dz == 2) try_pair(A, B);
-                        if (dz >= 2) break;
-                    }
-                } else {
-                    int dx, dy;
-                    fwd_col((int)o - 1, dx, dy);
-                    const bool near_col = dx <= 1 && dy >= -1 && dy <= 1;
-                    const uint32_t ns = sA + dx * kHW + dy;
-                    const uint32_t e = s_cend[ns];
-                    for (uint32_t B = s_cfirst[ns]; B < e; ++B) {
-                        const int32_t dz = z_of(B) - zA;
-                        if (dz > 2) break;
-                        if (dz < -2 || (near_col && dz >= -1 && dz <= 1)) continue;
-                        try_pair(A, B);
-                    }
-                }
-            }
-            __syncthreads();
-            TILE_PHASE(2);
-            // 5. Publish: a core cell's global parent becomes its LDS root
-            // (no other kernel writes these parents meanwhile: each cell is
-            // in one core); a halo cell that joined a core component is
-            // recorded as an edge, linked after all tiles.
-            auto gid_of = [&](uint32_t l) {
-                int lo = 0, hi = nseg - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_sl[mid] <= l) lo = mid;
-                    else hi = mid - 1;
-                }
-                return (int32_t)(s_sg[lo] + (l - s_sl[lo]));
-            };
-            const int lane = __lane_id();
-            for (uint32_t l0 = tid & ~63u; l0 < L; l0 += kBlock) {
-                const uint32_t l = l0 + (uint32_t)lane;
-                bool edge = false;
-                uint64_t ev = 0;
-                if (l < L) {
-                    const uint32_t r = lds_find(s_par, l);
-                    if (l < Lc) {
-                        if (r != l) cpar[gid_of(l)] = gid_of(r);
-                    } else if (r < Lc) {
-                        edge = true;
-                        ev = ((uint64_t)(uint32_t)gid_of(l) << 32) | (uint32_t)gid_of(r);
-                    }
-                }
-                const uint64_t em = __ballot(edge);
-                if (em) {
-                    uint32_t base = 0;
-                    if (lane == first_lane(em)) base = atomicAdd(&P->nedges, (uint32_t)__popcll(em));
-                    base = __shfl(base, first_lane(em));
-                    if (edge) {
-                        const uint32_t i = base + (uint32_t)__popcll(em & lanemask_lt());
-                        if (i < edge_cap) edges[i] = ev;
-                        else atomicExch(&P->status, kStatusDevice);
-                    }
-                }
-            }
-            TILE_PHASE(3);
-        }
-        __syncthreads();
-    }
-        if (tid == 0) s_chunk = next_chunk;
-    }
-#ifdef FEC_COUNTERS
-    if (level == 0) {
-        FEC_COUNT(P, 4, c_tests[0] + c_tests[1]);
-        FEC_COUNT(P, 5, c_evals[0]);
-        atomicMax(&P->counters[6], (unsigned long long)c_maxev);
-        FEC_COUNT(P, 7, c_evals[1]);
-    }
-#endif
-#undef TILE_PHASE
-}
-
-// Find with path halving: every visited node is pointed at its
-// grandparent.  The store goes to a node that is not a root, which no
-// compare-and-swap targets, and writes one of its ancestors (also when the
-// grandparent read was stale), so concurrent hooks are never undone.
-__device__ __forceinline__ int32_t uf_find_halve(int32_t *par, int32_t x) {
-    int32_t p = par[x];
-    while (p != x) {
-        const int32_t gp = par[p];
-        if (gp == p) return p;
-        par[x] = gp;
-        x = gp;
-        p = par[x];
-    }
-    return x;
-}
-
-__device__ __forceinline__ void uf_link_halve(int32_t *par, int32_t a, int32_t b) {
-    a = uf_find_halve(par, a);
-    b = uf_find_halve(par, b);
-    while (a != b) {
-        const bool ah = uf_rank(a) > uf_rank(b);
-        const int32_t hi = ah ? a : b, lo = ah ? b : a;
-        const int32_t old = atomicCAS(par + hi, hi, lo);
-        if (old == hi) return;
-        if (hi == a) a = uf_find_halve(par, old);
-        else b = uf_find_halve(par, old);
-    }
-}
-
-// Links the cross-tile edges recorded by the tile kernels.
-__global__ __launch_bounds__(kBlock) void k_link_edges(const uint64_t *__restrict__ edges,
-                                                       int32_t *cpar, const Params *__restrict__ P) {
-    if (P->status != kStatusOk || !P->use_tiles) return;
-    const uint32_t ne = P->nedges;
-    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < ne; i += gridDim.x * kBlock) {
-        const uint64_t e = edges[i];
-        uf_link_halve(cpar, (int32_t)(e >> 32), (int32_t)(e & 0xFFFFFFFFu));
-    }
-}
-
-// any_joined with the box filter of the second range: its box is gathered
-// first, then points of the first range out of reach of it are skipped.
-__device__ __forceinline__ bool any_joined_boxed(const float4 *__restrict__ spts, uint32_t sA,
-                                                 uint32_t eA, uint32_t sB, uint32_t eB,
-                                                 float d2) {
-    const float4 q = spts[sB];
-    float4 lo = q, hi = q;
-#pragma unroll 4
-    for (uint32_t b = sB + 1; b < eB; ++b) {
-        const float4 p = spts[b];
-        lo.x = fminf(lo.x, p.x); lo.y = fminf(lo.y, p.y); lo.z = fminf(lo.z, p.z);
-        hi.x = fmaxf(hi.x, p.x); hi.y = fmaxf(hi.y, p.y); hi.z = fmaxf(hi.z, p.z);
-    }
-    for (uint32_t a = sA; a < eA; ++a) {
-        const float4 pa = spts[a];
-        if (!(point_gap2(pa.x, pa.y, pa.z, lo, hi) < d2)) continue;
-        for (uint32_t b = sB; b < eB; ++b)
-            if (joined(pa.x, pa.y, pa.z, spts[b], d2)) return true;
-    }
-    return false;
-}
-
-// Per-cell pass over global memory for sub-tiles over the LDS capacity:
-// every forward offset of the 5x5x5 stencil of every core cell.
-__global__ __launch_bounds__(kBlock) void k_hook_cells(
-    const float4 *__restrict__ spts, const uint32_t *__restrict__ cell_start,
-    const uint64_t *__restrict__ cell_key, const uint32_t *__restrict__ col_cell,
-    const uint32_t *__restrict__ colgrid, const uint32_t *__restrict__ colbits,
-    const uint64_t *__restrict__ jobs, int32_t *cpar, const Params *__restrict__ P) {
-    if (P->status != kStatusOk || !P->use_tiles) return;
-    const uint32_t njobs = P->nglob;
-    const Grid g = grid_of(P);
-    const int64_t W = g.NYp / kTW;
-    const int64_t M = P->M;
-    const float d2 = P->d2;
-    for (uint32_t job = blockIdx.x; job < njobs; job += gridDim.x) {
-        int64_t cx0, ty;
-        int nrows;
-        tile_undesc(jobs[job], cx0, ty, nrows);
-        for (int r = 0; r < nrows; ++r) {
-            const int64_t cx = cx0 + r;
-            if (cx >= g.NX) break;
-            const uint32_t wc = colbits[cx * W + ty];
-            if (!wc) continue;
-            const int j0 = __ffs(wc) - 1;
-            const uint32_t id0 = colgrid[(uint64_t)(cx * g.NYp + ty * kTW + j0)];
-            const uint32_t c0 = col_cell[id0], c1 = col_cell[id0 + (uint32_t)__popc(wc)];
-            for (uint32_t A = c0 + threadIdx.x; A < c1; A += kBlock) {
-                const uint64_t key = cell_key[A];
-                const int64_t cz = (int64_t)(key & g.zmask);
-                int64_t ax, ay;
-                g.col_xy(key >> g.bz, ax, ay);
-                const uint32_t sA = cell_start[A], eA = cell_start[A + 1];
-                auto pair = [&](uint32_t B) {
-                    const int32_t ra = uf_find(cpar, (int32_t)A), rb = uf_find(cpar, (int32_t)B);
-                    if (ra == rb) return;
-                    if (any_joined_boxed(spts, sA, eA, cell_start[B], cell_start[B + 1], d2))
-                        uf_link(cpar, ra, rb);
-                };
-                for (uint32_t B = A + 1; (int64_t)B < M && B <= A + 2; ++B) {
-                    const uint64_t kb = cell_key[B];
-                    if ((kb >> g.bz) != (key >> g.bz)) break;
-                    const int64_t dz = (int64_t)(kb & g.zmask) - cz;
-                    if (dz > 2) break;
-                    pair(B);
-                }
-                for (int q = 0; q < 12; ++q) {
-                    int dx, dy;
-                    fwd_col(q, dx, dy);
-                    const int64_t nx = ax + dx, ny = ay + dy;
-                    if (nx >= g.NX || ny < 0 || ny >= g.NY) continue;
-                    const uint64_t idx = (uint64_t)(nx * g.NYp + ny);
-                    if (!((colbits[idx >> 5] >> (idx & 31)) & 1u)) continue;
-                    const uint32_t cid = colgrid[idx];
-                    const uint32_t b0 = col_cell[cid], b1 = col_cell[cid + 1];
-                    for (uint32_t B = b0; B < b1; ++B) {
-                        const int64_t dz = (int64_t)(cell_key[B] & g.zmask) - cz;
-                        if (dz > 2) break;
-                        if (dz >= -2) pair(B);
                     }
                 }
             }
@@ -2216,18 +1546,16 @@ __global__ void k_finish(const Params *__restrict__ P, int32_t *__restrict__ k_o
 
 const char *stage_name(int s) {
     static const char *names[kNumStages] = {
-        "bbox",      "plan",      "keys",       "sort_hist",  "sort_scan",   "sort_scatter",
-        "gather",    "tile_scan",
-        "cells",     "colgrid",   "tile_list",  "hook_tile",  "hook_subtile", "link_edges",
-        "hook_cells",
-        "runs",      "hook_near", "compress_1", "giant",      "work_list",   "hook_far",
-        "compress_2", "final_cells", "final_labels", "finish"};
+        "bbox",       "plan",      "keys",       "sort_hist",   "sort_scan",    "sort_scatter",
+        "gather",     "tile_scan", "cells",      "colgrid",     "runs",         "hook_near",
+        "compress_1", "giant",     "work_list",  "hook_far",    "compress_2",   "final_cells",
+        "final_labels", "finish"};
     return (s >= 0 && s < kNumStages) ? names[s] : "";
 }
 
 hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_size,
                            int32_t max_size, int32_t *labels_out, int32_t *k_out, void *ws,
-                           const Layout &L, hipStream_t st, Timer *timer, int hook_tiles) {
+                           const Layout &L, hipStream_t st, Timer *timer) {
     char *w = static_cast<char *>(ws);
     Params *P = reinterpret_cast<Params *>(w + L.params);
     float *partials = reinterpret_cast<float *>(w + L.partials);
@@ -2253,7 +1581,6 @@ hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_siz
     int32_t *blkhead = reinterpret_cast<int32_t *>(w + L.blkhead);
     uint64_t *gbits = reinterpret_cast<uint64_t *>(w + L.gbits);
     uint32_t *work = reinterpret_cast<uint32_t *>(w + L.work);
-    uint64_t *edges = reinterpret_cast<uint64_t *>(w + L.edges);
 
     const int64_t ntiles = L.ntiles;
     int nb_bbox = (int)((n + kBlock * 4 - 1) / (kBlock * 4));
@@ -2276,7 +1603,7 @@ hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_siz
 
     FEC_LAUNCH(kStBbox, k_bbox<<<nb_bbox, kBlock, 0, st>>>(xyz, n, partials));
     FEC_LAUNCH(kStPlan, k_plan<<<1, kBlock, 0, st>>>(partials, nb_bbox, P, n, d, min_size,
-                                                      max_size, L.colgrid_cap, hook_tiles));
+                                                      max_size, L.colgrid_cap));
     FEC_LAUNCH(kStKeys, k_keys<<<nb_stream, kBlock, 0, st>>>(xyz, P, keys0, vals0));
     for (int pass = 0; pass < max_passes; ++pass) {
         const uint64_t *src = (pass & 1) ? keys1 : keys0;
@@ -2298,38 +1625,20 @@ hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_siz
                              cpar, csize, ccanon));
     FEC_LAUNCH(kStColGrid, k_colgrid<<<nb_cells, kBlock, 0, st>>>(col_key, col_cell, cell_start,
                                                                    colgrid, colbits, P));
-    // dense index: tiles in LDS (the kernels below return at once otherwise)
-    const uint32_t list_cap = (uint32_t)(n > 0 ? n : 1);
-    const uint32_t sub_cap = list_cap / 2, glob_cap = list_cap - list_cap / 2;
-    uint64_t *tiles = keys0;             // free once the cell table is built
-    uint64_t *subtiles = keys1;
-    uint64_t *globrows = keys1 + sub_cap;
-    FEC_LAUNCH(kStTileList, k_tile_list<<<nb_cells, kBlock, 0, st>>>(colbits, tiles, list_cap, P));
-    const uint32_t edge_cap = (uint32_t)L.edge_cap;
-    FEC_LAUNCH(kStHookTile, k_hook_tile<kTileCapP, kTileCapC><<<kTileBlocks, kBlock, 0, st>>>(
-                                spts, cell_start, cell_key, col_cell, colgrid, colbits, tiles, 0,
-                                subtiles, sub_cap, edges, edge_cap, cpar, P));
-    FEC_LAUNCH(kStHookRows, k_hook_tile<kTileCapP, kTileCapC><<<kTileBlocks, kBlock, 0, st>>>(
-                                spts, cell_start, cell_key, col_cell, colgrid, colbits, subtiles,
-                                1, globrows, glob_cap, edges, edge_cap, cpar, P));
-    FEC_LAUNCH(kStLinkEdges, k_link_edges<<<nb_cells, kBlock, 0, st>>>(edges, cpar, P));
-    FEC_LAUNCH(kStHookCells, k_hook_cells<<<kTileBlocks, kBlock, 0, st>>>(
-                                 spts, cell_start, cell_key, col_cell, colgrid, colbits, globrows,
-                                 cpar, P));
-    // per cell: boxes, runs, near shell, giant component, far shell
+    // runs, near shell, giant component, far shell
     FEC_LAUNCH(kStRuns, k_runs1<<<(unsigned)ntiles, kBlock, 0, st>>>(spts, cell_start, cell_key,
                                                                       heads, blkhead, P));
     FEC_LAUNCH(kStRuns, k_runs2<<<(unsigned)ntiles, kBlock, 0, st>>>(heads, blkhead, cpar, P));
     FEC_LAUNCH(kStHookNear, k_hook_near<<<nb_cells, kBlock, 0, st>>>(
                                 spts, cell_start, cell_key, col_key, col_cell, colgrid, colbits,
                                 cpar, P));
-    FEC_LAUNCH(kStCompress1, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P, 0));
+    FEC_LAUNCH(kStCompress1, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P));
     FEC_LAUNCH(kStGiant, k_giant<<<1, 1024, 0, st>>>(cpar, P));
     FEC_LAUNCH(kStWorkList, k_nongiant<<<nb_cells, kBlock, 0, st>>>(cpar, gbits, work, P));
     FEC_LAUNCH(kStHookFar, k_hook_far<<<nb_cells, kBlock, 0, st>>>(
                                 spts, cell_start, cell_key, col_key, col_cell, colgrid, colbits,
                                 gbits, work, cpar, P));
-    FEC_LAUNCH(kStCompress2, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P, 1));
+    FEC_LAUNCH(kStCompress2, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P));
     FEC_LAUNCH(kStFinalCells, k_final_cells<<<nb_cells, kBlock, 0, st>>>(
                                   cpar, cell_start, sorig, csize, ccanon, P));
     FEC_LAUNCH(kStFinalLabels, k_final_labels<<<nb_cells, kBlock, 0, st>>>(

@@ -54,13 +54,6 @@ struct Params {
     int32_t giant;        // root of the largest component after sampling (-1: none)
     uint32_t nwork;       // cells outside that component (full-stencil work list)
     uint32_t pad1;
-    uint32_t ntile;       // occupied tiles (dense index)
-    uint32_t nsub;        // tile rows re-run one at a time (tiles over the LDS capacity)
-    uint32_t nglob;       // tile rows over the LDS capacity (cell-by-cell pass)
-    int32_t use_tiles;    // 1: hooking by tiles in LDS (dense index), 0: per cell
-    uint32_t ticket_tile[2][8];  // work counters of the tile kernels (per level)
-    uint32_t nedges;      // cross-tile links left by the tile kernels
-    uint32_t pad3;
     int32_t kept;         // kept clusters
     int32_t max_cell;     // largest number of points in one cell
     unsigned long long counters[8];  // diagnostic event counts (counting builds only)
@@ -72,8 +65,7 @@ struct Layout {
     size_t params, partials, tile_cnt, tile_off;
     size_t keys0, keys1, vals0, vals1, th;
     size_t spts, sorig, cell_start, cell_key, cpar, csize, ccanon;
-    size_t col_key, col_cell, colgrid, colbits, heads, blkhead, gbits, work, edges;
-    uint64_t edge_cap;
+    size_t col_key, col_cell, colgrid, colbits, heads, blkhead, gbits, work;
     uint64_t colgrid_cap;
     size_t total;
     int64_t ntiles;
@@ -123,9 +115,6 @@ inline Layout make_layout(int64_t n) {
     L.blkhead = take((size_t)L.ntiles * sizeof(int32_t));
     L.gbits = take((un / 64 + 1) * sizeof(uint64_t));
     L.work = take(un * sizeof(uint32_t));
-    L.edge_cap = 2 * (uint64_t)un;  // links between tiles (tile hooking only)
-    if (L.edge_cap > 0xFFFFFFFFull) L.edge_cap = 0xFFFFFFFFull;
-    L.edges = take((size_t)L.edge_cap * sizeof(uint64_t));
     L.total = off;
     return L;
 }
@@ -142,11 +131,6 @@ enum Stage : int {
     kStTileScan,
     kStCells,
     kStColGrid,
-    kStTileList,
-    kStHookTile,
-    kStHookRows,
-    kStLinkEdges,
-    kStHookCells,
     kStRuns,
     kStHookNear,
     kStCompress1,
@@ -170,10 +154,8 @@ struct Timer {
 };
 
 // Enqueues the whole pipeline.  Returns hipSuccess or the first launch error.
-// hook_tiles: 1 = hook by tiles in LDS where the dense column index applies,
-// 0 = per cell everywhere.
 hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_size,
                            int32_t max_size, int32_t *labels_out, int32_t *k_out, void *ws,
-                           const Layout &L, hipStream_t stream, Timer *timer, int hook_tiles);
+                           const Layout &L, hipStream_t stream, Timer *timer);
 
 }  // namespace fec

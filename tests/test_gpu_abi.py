@@ -87,13 +87,22 @@ def test_workspace_stats_and_profile():
     assert prof["hook_near"][1] == 1 and prof["hook_near"][0] > 0
 
 
-def test_hooking_mode_switch():
-    import paper_2208_07678_amd as fec
-    prev = fec.set_hooking(fec.HOOK_TILES)
-    try:
-        with pytest.raises(fec.FecError) as ei:
-            fec.set_hooking(7)
-        assert ei.value.code == fec.FEC_EINVAL
-        assert fec.set_hooking(fec.HOOK_TILES) == fec.HOOK_TILES
-    finally:
-        fec.set_hooking(prev)
+def test_library_first_then_torch_in_fresh_process():
+    # the binding loads its library before torch has touched the GPU (one HIP
+    # runtime in the process either way)
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import paper_2208_07678_amd as fec\n"
+        "print(fec.version())\n"
+        "import numpy as np, torch\n"
+        "x = torch.tensor([[0, 0, 0], [0.5, 0, 0], [5, 5, 5]], dtype=torch.float32).cuda()\n"
+        "labels, k = fec.cluster(x, 1.0, 1, 10)\n"
+        "print(labels.cpu().tolist(), k)\n" % root)
+    say("fresh process")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip().splitlines()[-1] == "[0, 0, 2] 2"
