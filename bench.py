@@ -108,12 +108,119 @@ def measured_traffic(kernel: str):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
+def bench_batch(args) -> None:
+    """Frames/s of the batched form on the 64-frame batch, beside 64 plain
+    per-frame calls on the same resident frames (one JSON line)."""
+    import torch
+
+    import paper_2208_07678_amd as fec
+    import synth
+
+    t_gen = time.perf_counter()
+    frames, ds, mn, mx = synth.make_batch_config(args.workload)
+    t_gen = time.perf_counter() - t_gen
+    nf = len(frames)
+    dev = torch.device("cuda:0")
+    xs = [torch.from_numpy(f).to(dev) for f in frames]
+    xyz, offs = fec.pack_frames(xs)
+    n = xyz.shape[0]
+    print("bench: workload %s %d frames n=%d generated in %.1f s" % (args.workload, nf, n, t_gen),
+          file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream(dev)
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    kdev = torch.empty(nf, dtype=torch.int32, device=dev)
+    ws = fec.new_batch_workspace(n, nf, dev)
+    d_t = torch.tensor(ds, dtype=torch.float32, device=dev)
+    lo_t = torch.full((nf,), mn, dtype=torch.int32, device=dev)
+    hi_t = torch.full((nf,), mx, dtype=torch.int32, device=dev)
+
+    def step():
+        fec.cluster_batch_async(xyz, offs, d_t, lo_t, hi_t, labels=labels, k_out=kdev,
+                                workspace=ws, stream=stream)
+
+    # the same frames, one plain call each (labels into the same buffer)
+    seq_ws = fec.new_workspace(max(int(t.shape[0]) for t in xs), dev)
+    seq_k = torch.empty(nf, dtype=torch.int32, device=dev)
+    bounds = [int(v) for v in offs.cpu().tolist()]
+    seq_labels = [labels[bounds[b]:bounds[b + 1]] for b in range(nf)]
+
+    def step_seq():
+        for b in range(nf):
+            fec.cluster_async(xs[b], ds[b], mn, mx, labels=seq_labels[b], k_out=seq_k[b:b + 1],
+                              workspace=seq_ws, stream=stream)
+
+    def timed(fn, steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    for _ in range(args.warmup):
+        step_seq()
+    torch.cuda.synchronize()
+    ks_seq = seq_k.cpu().tolist()
+    labels_seq = labels.clone()
+    seq_ms = timed(step_seq, args.steps)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ks = kdev.cpu().tolist()
+    if min(ks) < 0:
+        raise SystemExit("bench: device status %s" % ks)
+    if ks != ks_seq or not torch.equal(labels, labels_seq):
+        raise SystemExit("bench: batched and per-frame results differ")
+
+    fec.profile_reset()
+    fec.profile_enable()
+    step()
+    torch.cuda.synchronize()
+    prof_all = fec.profile_read()
+    fec.profile_reset()
+    dominant = max(prof_all, key=lambda s: prof_all[s][0])
+    fec.profile_enable([dominant])
+    ms_per_step = timed(step, args.steps)
+    dom_ms, dom_launches = fec.profile_read()[dominant]
+    fec.profile_enable([])
+    avg_launch_ms = dom_ms / max(dom_launches, 1)
+    bytes_per_launch = ALG_BYTES_PER_POINT.get(dominant, 16.0) * n
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    out = {
+        "metric": "frames/s clustered (64-frame batch)",
+        "value": nf / (ms_per_step * 1e-3),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "frames": nf, "n_points": n,
+                   "d_values": sorted(set(ds)), "min_size": mn, "max_size": mx,
+                   "clusters_kept": int(sum(ks))},
+        "sequential": {"ms_per_batch": seq_ms, "frames_per_s": nf / (seq_ms * 1e-3),
+                       "speedup": seq_ms / ms_per_step},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dominant,
+                     "avg_launch_ms": avg_launch_ms, "alg_bytes_per_launch": bytes_per_launch},
+        "cpu_baseline": None,
+    }
+    if args.stages:
+        out["stage_ms_per_call"] = {s: round(v[0], 4) for s, v in prof_all.items()}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="map27m", choices=["map27m", "lidar120k", "blobs20k"])
+    ap.add_argument("--workload", default="map27m",
+                    choices=["map27m", "lidar120k", "blobs20k", "batch64"])
     ap.add_argument("--cpu-frames", type=int, default=30,
                     help="map frames in the CPU-baseline sample (0 = skip)")
     ap.add_argument("--stages", action="store_true", help="also print a per-stage breakdown")
@@ -129,6 +236,10 @@ def main():
               "(the multi-GPU slab decomposition is a design note, not code)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch64":
+        bench_batch(args)
+        return
 
     import numpy as np  # noqa: F401
     import synth

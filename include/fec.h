@@ -88,6 +88,52 @@ int32_t fec_cluster_async(const float *xyz, int64_t n, float d, int32_t min_size
                           int32_t max_size, int32_t *labels_out, int32_t *k_out, void *workspace,
                           size_t workspace_bytes, void *stream);
 
+/*
+ * Batched form: many independent clouds ("frames") in one call, each with its
+ * own threshold and size bounds -- the result for every frame is exactly what
+ * fec_cluster_async returns for that frame alone (same Sec. 2.2 / Eq. (1) /
+ * Alg. 1 computation), but the whole batch shares one sort and one launch
+ * sequence.
+ *
+ *   xyz        float32 [n_total][3], the frames' points one frame after the
+ *              other (DEVICE, read only).
+ *   offsets    int64 [nframes + 1] (DEVICE): frame f holds the points
+ *              offsets[f] .. offsets[f+1]-1; offsets[0] == 0,
+ *              offsets[nframes] == n_total, non-decreasing (empty frames are
+ *              allowed).
+ *   d          float32 [nframes] (DEVICE): the frame's threshold.
+ *   min_size, max_size  int32 [nframes] (DEVICE): the frame's inclusive size
+ *              bounds (min_size <= 0 acts as 1).
+ *   labels_out int32 [n_total] (DEVICE, written): FRAME-LOCAL labels -- for a
+ *              point of frame f, the smallest index in its cluster counted
+ *              from offsets[f] (i.e. the label fec_cluster gives on that frame
+ *              alone), or -1.
+ *   k_out      int32 [nframes] (DEVICE, written): per frame, the number of
+ *              kept clusters, or FEC_EINVAL when that frame's d / bounds fail
+ *              the checks fec_cluster applies on the host (d finite, > 0,
+ *              d*d a normal binary32 number, min_size <= max_size), or
+ *              FEC_ERANGE when its extent needs a grid coordinate of 2^31 or
+ *              more cells.  Such a frame's labels are all -1; other frames are
+ *              unaffected.  When the offsets are not a partition of
+ *              [0, n_total) every k_out entry is FEC_EINVAL and every label
+ *              -1; when the stacked grid of all frames needs a key of more
+ *              than 64 bits every entry is FEC_ERANGE.
+ *   workspace  DEVICE, >= fec_batch_workspace_bytes(n_total, nframes) bytes,
+ *              256-byte aligned.
+ * Host-side checks (FEC_EINVAL, nothing launched): n_total outside
+ * [0, 2^31 - 1]; nframes outside [1, 65536]; a null offsets, d, min_size,
+ * max_size or k_out; null xyz or labels_out with n_total > 0; workspace null,
+ * too small or misaligned.  Returns FEC_OK once enqueued, FEC_EDEVICE when a
+ * launch fails.  Same stream / workspace rules as fec_cluster_async.
+ */
+int32_t fec_cluster_batch_async(const float *xyz, int64_t n_total, int32_t nframes,
+                                const int64_t *offsets, const float *d, const int32_t *min_size,
+                                const int32_t *max_size, int32_t *labels_out, int32_t *k_out,
+                                void *workspace, size_t workspace_bytes, void *stream);
+
+/* Workspace bytes of fec_cluster_batch_async (0 for invalid sizes). */
+size_t fec_batch_workspace_bytes(int64_t n_total, int32_t nframes);
+
 /* Stream used by fec_cluster (a hipStream_t; NULL = null stream).  Returns FEC_OK. */
 int32_t fec_set_stream(void *stream);
 

@@ -8,6 +8,7 @@ kernels.  There is no CPU fallback: every entry point raises when the built
 library is missing, and tensors must live on the GPU.
 
     labels, k = paper_2208_07678_amd.cluster(xyz, d, min_size, max_size)
+    labels, k = paper_2208_07678_amd.cluster_batch(xyz_all, offsets, d, min_size, max_size)
 
 ``xyz`` is a contiguous float32 CUDA tensor [n, 3]; ``labels`` is an int32
 CUDA tensor [n] with the smallest point index of each kept cluster, -1 for
@@ -21,6 +22,7 @@ import os
 
 __all__ = [
     "cluster", "cluster_async", "workspace_bytes", "workspace_stats", "FecError",
+    "cluster_batch", "cluster_batch_async", "batch_workspace_bytes", "pack_frames",
     "profile_enable", "profile_read", "profile_reset", "stage_names", "lib_path",
     "FEC_OK", "FEC_EINVAL", "FEC_ERANGE", "FEC_ENOMEM", "FEC_EDEVICE",
 ]
@@ -57,6 +59,9 @@ def _load():
         "fec_cluster": ([vp, i64, f32, i32, i32, vp], i32),
         "fec_workspace_bytes": ([i64], ctypes.c_size_t),
         "fec_cluster_async": ([vp, i64, f32, i32, i32, vp, vp, vp, ctypes.c_size_t, vp], i32),
+        "fec_cluster_batch_async": ([vp, i64, i32, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t,
+                                     vp], i32),
+        "fec_batch_workspace_bytes": ([i64, i32], ctypes.c_size_t),
         "fec_set_stream": ([vp], i32),
         "fec_release": ([], None),
         "fec_last_error": ([], ctypes.c_char_p),
@@ -78,6 +83,7 @@ def _load():
 
 EXPORTED = [
     "fec_cluster", "fec_workspace_bytes", "fec_cluster_async", "fec_set_stream", "fec_release",
+    "fec_cluster_batch_async", "fec_batch_workspace_bytes",
     "fec_last_error", "fec_version", "fec_workspace_stats", "fec_profile_enable",
     "fec_profile_read", "fec_profile_reset", "fec_stage_count", "fec_stage_name",
 ]
@@ -175,6 +181,111 @@ def cluster(xyz, d: float, min_size: int = 1, max_size: int = 2**31 - 1, *,
     if k < 0:
         raise FecError(k, "device-side status %d" % k)
     return labels, k
+
+
+def batch_workspace_bytes(n_total: int, nframes: int) -> int:
+    return int(_load().fec_batch_workspace_bytes(int(n_total), int(nframes)))
+
+
+def new_batch_workspace(n_total: int, nframes: int, device):
+    """A device workspace (uint8 tensor) for a batch of n_total points in nframes frames."""
+    torch = _torch()
+    nb = batch_workspace_bytes(n_total, nframes)
+    if nb <= 0:
+        raise ValueError("bad batch sizes n_total=%d nframes=%d" % (n_total, nframes))
+    return torch.empty(nb + 256, dtype=torch.uint8, device=device)
+
+
+def _per_frame(v, nframes: int, dtype, dev):
+    """A device tensor [nframes] from a scalar, a sequence or a tensor."""
+    torch = _torch()
+    if isinstance(v, torch.Tensor):
+        t = v.to(device=dev, dtype=dtype).reshape(-1)
+    else:
+        if isinstance(v, (int, float)):
+            v = [v] * nframes
+        t = torch.tensor(list(v), dtype=dtype, device=dev)
+    if t.numel() != nframes:
+        raise ValueError("per-frame argument has %d values for %d frames" % (t.numel(), nframes))
+    return t.contiguous()
+
+
+def pack_frames(frames):
+    """Concatenates a list of float32 CUDA tensors [n_f, 3] into (xyz [sum n_f, 3], offsets).
+
+    offsets is an int64 CUDA tensor [len(frames) + 1].
+    """
+    torch = _torch()
+    if not frames:
+        raise ValueError("no frames")
+    for t in frames:
+        _check_xyz(t)
+    dev = frames[0].device
+    sizes = [int(t.shape[0]) for t in frames]
+    offs = [0]
+    for k in sizes:
+        offs.append(offs[-1] + k)
+    xyz = torch.cat(frames, 0) if len(frames) > 1 else frames[0]
+    return xyz.contiguous(), torch.tensor(offs, dtype=torch.int64, device=dev)
+
+
+def cluster_batch_async(xyz, offsets, d, min_size=1, max_size=2**31 - 1, *, labels=None,
+                        k_out=None, workspace=None, stream=None):
+    """Enqueues the clustering of a batch of frames (see fec_cluster_batch_async).
+
+    xyz float32 CUDA [n_total, 3]; offsets int64 [nframes + 1] (CUDA tensor, or
+    a sequence copied to the device); d, min_size, max_size per frame (scalar,
+    sequence or tensor).  Returns (labels int32 [n_total] frame-local,
+    k_out int32 [nframes], workspace) written when the stream gets there.
+    """
+    torch = _torch()
+    _check_xyz(xyz)
+    dev = xyz.device
+    n = xyz.shape[0]
+    if isinstance(offsets, torch.Tensor):
+        offs = offsets.to(device=dev, dtype=torch.int64).contiguous()
+    else:
+        offs = torch.tensor(list(offsets), dtype=torch.int64, device=dev)
+    nframes = offs.numel() - 1
+    if nframes < 1:
+        raise ValueError("offsets needs at least two entries")
+    d_t = _per_frame(d, nframes, torch.float32, dev)
+    lo_t = _per_frame(min_size, nframes, torch.int32, dev)
+    hi_t = _per_frame(max_size, nframes, torch.int32, dev)
+    if labels is None:
+        labels = torch.empty(n, dtype=torch.int32, device=dev)
+    if k_out is None:
+        k_out = torch.empty(nframes, dtype=torch.int32, device=dev)
+    if workspace is None:
+        workspace = new_batch_workspace(n, nframes, dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    wptr, wbytes = _aligned_ptr(workspace)
+    with torch.cuda.device(dev):
+        rc = _load().fec_cluster_batch_async(
+            ctypes.c_void_p(xyz.data_ptr()), n, nframes, ctypes.c_void_p(offs.data_ptr()),
+            ctypes.c_void_p(d_t.data_ptr()), ctypes.c_void_p(lo_t.data_ptr()),
+            ctypes.c_void_p(hi_t.data_ptr()), ctypes.c_void_p(labels.data_ptr()),
+            ctypes.c_void_p(k_out.data_ptr()), ctypes.c_void_p(wptr), wbytes,
+            ctypes.c_void_p(stream.cuda_stream))
+    if rc != FEC_OK:
+        _raise(rc)
+    # keep the argument tensors alive until the stream has used them
+    for t in (offs, d_t, lo_t, hi_t):
+        t.record_stream(stream)
+    return labels, k_out, workspace
+
+
+def cluster_batch(xyz, offsets, d, min_size=1, max_size=2**31 - 1, *, workspace=None,
+                  labels=None, stream=None):
+    """Clusters a batch of frames; returns (frame-local labels [n_total], k per frame list).
+
+    A frame whose arguments are refused reports its negative FEC_* status in
+    the list instead of a count (its labels are -1).
+    """
+    labels, k_out, _ = cluster_batch_async(xyz, offsets, d, min_size, max_size, labels=labels,
+                                           workspace=workspace, stream=stream)
+    return labels, [int(v) for v in k_out.cpu().tolist()]
 
 
 def workspace_stats(workspace, stream=None) -> dict:

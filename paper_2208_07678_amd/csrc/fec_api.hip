@@ -150,11 +150,62 @@ int32_t fec_cluster_async(const float *xyz, int64_t n, float d, int32_t min_size
                     workspace_bytes, L.total);
     if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0)
         return fail(FEC_EINVAL, "workspace is not 256-byte aligned");
+    fec::CallArgs a{};
+    a.xyz = xyz;
+    a.n = n;
+    a.nframes = 1;
+    a.d = d;
+    a.min_size = min_size;
+    a.max_size = max_size;
+    a.labels_out = labels_out;
+    a.k_out = k_out;
     hipError_t e;
     {
         std::lock_guard<std::mutex> lock(g_mu);
-        e = fec::launch_pipeline(xyz, n, d, min_size, max_size, labels_out, k_out, workspace, L,
-                                 st, g_timer.mask ? &g_timer : nullptr);
+        e = fec::launch_pipeline(a, workspace, L, st, g_timer.mask ? &g_timer : nullptr);
+    }
+    if (e != hipSuccess) return fail(FEC_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+size_t fec_batch_workspace_bytes(int64_t n_total, int32_t nframes) {
+    if (n_total < 0 || nframes < 1 || nframes > fec::kMaxFrames) return 0;
+    return fec::make_layout(n_total, nframes).total;
+}
+
+int32_t fec_cluster_batch_async(const float *xyz, int64_t n_total, int32_t nframes,
+                                const int64_t *offsets, const float *d, const int32_t *min_size,
+                                const int32_t *max_size, int32_t *labels_out, int32_t *k_out,
+                                void *workspace, size_t workspace_bytes, void *stream) {
+    if (n_total < 0 || n_total > 2147483647LL)
+        return fail(FEC_EINVAL, "n_total=%lld outside [0, 2^31-1]", (long long)n_total);
+    if (nframes < 1 || nframes > fec::kMaxFrames)
+        return fail(FEC_EINVAL, "nframes=%d outside [1, %d]", nframes, fec::kMaxFrames);
+    if (!offsets || !d || !min_size || !max_size || !k_out)
+        return fail(FEC_EINVAL, "null offsets, d, min_size, max_size or k_out");
+    if (n_total > 0 && (xyz == nullptr || labels_out == nullptr))
+        return fail(FEC_EINVAL, "null xyz or labels_out with n_total=%lld", (long long)n_total);
+    const fec::Layout L = fec::make_layout(n_total, nframes);
+    if (workspace == nullptr || workspace_bytes < L.total)
+        return fail(FEC_EINVAL, "workspace of %zu bytes is smaller than the %zu needed",
+                    workspace_bytes, L.total);
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0)
+        return fail(FEC_EINVAL, "workspace is not 256-byte aligned");
+    fec::CallArgs a{};
+    a.xyz = xyz;
+    a.n = n_total;
+    a.nframes = nframes;
+    a.offsets = offsets;
+    a.d_arr = d;
+    a.min_arr = min_size;
+    a.max_arr = max_size;
+    a.labels_out = labels_out;
+    a.k_out = k_out;
+    hipError_t e;
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        e = fec::launch_pipeline(a, workspace, L, static_cast<hipStream_t>(stream),
+                                 g_timer.mask ? &g_timer : nullptr);
     }
     if (e != hipSuccess) return fail(FEC_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return ok();

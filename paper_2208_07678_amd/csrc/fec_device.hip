@@ -119,14 +119,36 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_tmp,
 }
 
 // ------------------------------------------------------------- 1. bbox
-// Per-block min/max of the finite points and their count.
+// The point range of frame f: [0, n) for a single cloud, else the caller's
+// offsets clamped into [0, n] (the planning kernel refuses a batch whose
+// offsets do not partition [0, n), so clamping only keeps reads in range).
+__device__ __forceinline__ void frame_range(const int64_t *offs, int64_t n, int f, int64_t &lo,
+                                            int64_t &hi) {
+    if (!offs) {
+        lo = 0;
+        hi = n;
+        return;
+    }
+    int64_t a = offs[f], b = offs[f + 1];
+    a = a < 0 ? 0 : (a > n ? n : a);
+    b = b < a ? a : (b > n ? n : b);
+    lo = a;
+    hi = b;
+}
+
+// Per-block min/max of the finite points of one frame and their count;
+// block f * per_frame + j takes the j-th share of frame f.
 __global__ __launch_bounds__(kBlock) void k_bbox(const float *__restrict__ xyz, int64_t n,
+                                                 const int64_t *__restrict__ offs, int per_frame,
                                                  float *__restrict__ partials) {
+    const int f = blockIdx.x / per_frame, j = blockIdx.x % per_frame;
+    int64_t lo, hi;
+    frame_range(offs, n, f, lo, hi);
     float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY;
     float hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
     uint32_t cnt = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
+    for (int64_t i = lo + (int64_t)j * kBlock + threadIdx.x; i < hi;
+         i += (int64_t)per_frame * kBlock) {
         const float x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
         if (finite3(x, y, z)) {
             lo0 = fminf(lo0, x); lo1 = fminf(lo1, y); lo2 = fminf(lo2, z);
@@ -164,87 +186,178 @@ __global__ __launch_bounds__(kBlock) void k_bbox(const float *__restrict__ xyz, 
 }
 
 // ------------------------------------------------------------- 2. plan
-// Reduces the partial boxes and fixes the grid, the key layout and the
-// number of radix passes.  One block.
-__global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ partials, int nparts,
-                                                 Params *__restrict__ P, int64_t n, float d,
-                                                 int32_t min_size, int32_t max_size,
-                                                 uint64_t colgrid_cap) {
-    float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY;
-    float hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
-    uint64_t cnt = 0;
-    for (int b = threadIdx.x; b < nparts; b += kBlock) {
-        const float *q = partials + (size_t)b * 8;
-        lo0 = fminf(lo0, q[0]); lo1 = fminf(lo1, q[1]); lo2 = fminf(lo2, q[2]);
-        hi0 = fmaxf(hi0, q[3]); hi1 = fmaxf(hi1, q[4]); hi2 = fmaxf(hi2, q[5]);
-        cnt += __float_as_uint(q[6]);
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        lo0 = fminf(lo0, __shfl_xor(lo0, o)); lo1 = fminf(lo1, __shfl_xor(lo1, o));
-        lo2 = fminf(lo2, __shfl_xor(lo2, o)); hi0 = fmaxf(hi0, __shfl_xor(hi0, o));
-        hi1 = fmaxf(hi1, __shfl_xor(hi1, o)); hi2 = fmaxf(hi2, __shfl_xor(hi2, o));
-        cnt += __shfl_xor(cnt, o);
-    }
-    __shared__ float s[kBlock / 64][6];
-    __shared__ uint64_t sc[kBlock / 64];
+// Block-wide exclusive scan of 64-bit values (kBlock threads).
+__device__ __forceinline__ int64_t block_excl_scan_i64(int64_t v, int64_t *s_tmp, int64_t &total) {
+    const int lane = __lane_id();
     const int wave = threadIdx.x >> 6;
-    if (__lane_id() == 0) {
-        s[wave][0] = lo0; s[wave][1] = lo1; s[wave][2] = lo2;
-        s[wave][3] = hi0; s[wave][4] = hi1; s[wave][5] = hi2;
-        sc[wave] = cnt;
+    int64_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
     }
+    if (lane == 63) s_tmp[wave] = x;
+    __syncthreads();
+    int64_t before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        const int64_t t = s_tmp[w];
+        before += (w < wave) ? t : 0;
+        tot += t;
+    }
+    __syncthreads();
+    total = tot;
+    return before + x - v;
+}
+
+// Fixes every frame's grid, stacks the frames' grids along x, and fixes the
+// key layout and the number of radix passes.  One block: wave w plans the
+// frames w, w + 4, ...; then the block scans the frames' widths.
+__global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ partials,
+                                                 int per_frame, Params *__restrict__ P,
+                                                 Frame *__restrict__ frames, int nframes,
+                                                 int64_t n, const int64_t *__restrict__ offs,
+                                                 const float *__restrict__ d_arr,
+                                                 const int32_t *__restrict__ min_arr,
+                                                 const int32_t *__restrict__ max_arr, float d_one,
+                                                 int32_t min_one, int32_t max_one,
+                                                 uint64_t colgrid_cap) {
+    __shared__ int64_t s_tmp[kBlock / 64];
+    __shared__ int32_t s_bad;
+    const int wave = threadIdx.x >> 6, lane = __lane_id();
     for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kBlock) (&P->hist[0][0])[i] = 0;
     if (threadIdx.x < 8) P->counters[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
+
+    for (int f = wave; f < nframes; f += kBlock / 64) {
+        float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY;
+        float hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
+        uint64_t cnt = 0;
+        for (int b = lane; b < per_frame; b += 64) {
+            const float *q = partials + ((size_t)f * per_frame + b) * 8;
+            lo0 = fminf(lo0, q[0]); lo1 = fminf(lo1, q[1]); lo2 = fminf(lo2, q[2]);
+            hi0 = fmaxf(hi0, q[3]); hi1 = fmaxf(hi1, q[4]); hi2 = fmaxf(hi2, q[5]);
+            cnt += __float_as_uint(q[6]);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            lo0 = fminf(lo0, __shfl_xor(lo0, o)); lo1 = fminf(lo1, __shfl_xor(lo1, o));
+            lo2 = fminf(lo2, __shfl_xor(lo2, o)); hi0 = fmaxf(hi0, __shfl_xor(hi0, o));
+            hi1 = fmaxf(hi1, __shfl_xor(hi1, o)); hi2 = fmaxf(hi2, __shfl_xor(hi2, o));
+            cnt += __shfl_xor(cnt, o);
+        }
+        if (lane != 0) continue;
+        Frame F;
+        if (offs) {
+            const int64_t a = offs[f], b = offs[f + 1];
+            if (a > b || (f == 0 && a != 0) || (f == nframes - 1 && b != n)) s_bad = 1;
+        }
+        frame_range(offs, n, f, F.off0, F.off1);
+        F.d = d_arr ? d_arr[f] : d_one;
+        const int32_t mn = min_arr ? min_arr[f] : min_one;
+        F.max_size = max_arr ? max_arr[f] : max_one;
+        F.min_size = mn < 1 ? 1 : mn;
+        F.d2 = __fmul_rn(F.d, F.d);
+        F.status = kStatusOk;
+        // the same argument checks as the host applies to a single cloud
+        if (!isfinite(F.d) || !(F.d > 0.0f) || !(F.d2 >= FLT_MIN) || isinf(F.d2) ||
+            mn > F.max_size)
+            F.status = kStatusInval;
+        F.kept = 0;
+        F.giant = -1;
+        F.cell0 = 0;
+        F.xoff = 0;
+        int64_t N3[3] = {1, 1, 1};
+        double o3[3] = {0.0, 0.0, 0.0};
+        const float r[6] = {lo0, lo1, lo2, hi0, hi1, hi2};
+        double inv = 0.0;
+        if (F.status == kStatusOk) {
+            const double side = (double)F.d * (1.0 - 0x1p-10) / sqrt(3.0);
+            inv = 1.0 / side;
+            if (cnt > 0) {
+                for (int a = 0; a < 3; ++a) {
+                    o3[a] = (double)r[a];
+                    const double ext = ((double)r[a + 3] - (double)r[a]) * inv;
+                    if (!(ext < 0x1p31)) {
+                        F.status = kStatusRange;
+                    } else {
+                        N3[a] = (int64_t)floor(ext) + 1;
+                    }
+                }
+            }
+        }
+        if (F.status != kStatusOk) {  // a refused frame holds no cell
+            inv = 0.0;
+            N3[0] = N3[1] = N3[2] = 1;
+            o3[0] = o3[1] = o3[2] = 0.0;
+            cnt = 0;
+        }
+        F.nvalid = (int64_t)cnt;
+        F.inv_s = inv;
+        F.ox = o3[0]; F.oy = o3[1]; F.oz = o3[2];
+        F.NX = N3[0]; F.NY = N3[1]; F.NZ = N3[2];
+        frames[f] = F;
+    }
+    __syncthreads();
+
+    // x offsets: NX of every earlier frame plus a gap of two empty columns
+    __shared__ unsigned long long s_ny, s_nz, s_nv;
+    if (threadIdx.x == 0) s_ny = s_nz = 1, s_nv = 0;
+    int64_t carry = 0;
+    for (int c0 = 0; c0 < nframes; c0 += kBlock) {
+        const int f = c0 + threadIdx.x;
+        const bool in = f < nframes;
+        const int64_t w = in ? frames[f].NX + 2 : 0;
+        int64_t tot;
+        const int64_t before = block_excl_scan_i64(w, s_tmp, tot);
+        if (in) frames[f].xoff = carry + before;
+        carry += tot;
+        uint64_t ny = in ? (uint64_t)frames[f].NY : 1, nz = in ? (uint64_t)frames[f].NZ : 1;
+        uint64_t nv = in ? (uint64_t)frames[f].nvalid : 0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint64_t a = __shfl_xor(ny, o), b = __shfl_xor(nz, o);
+            ny = a > ny ? a : ny;
+            nz = b > nz ? b : nz;
+            nv += __shfl_xor(nv, o);
+        }
+        if (lane == 0) {
+            atomicMax(&s_ny, (unsigned long long)ny);
+            atomicMax(&s_nz, (unsigned long long)nz);
+            atomicAdd(&s_nv, (unsigned long long)nv);
+        }
+    }
+    __syncthreads();
+    const int64_t NY = (int64_t)s_ny, NZ = (int64_t)s_nz, nvalid = (int64_t)s_nv;
     if (threadIdx.x != 0) return;
 
-    float r[6] = {s[0][0], s[0][1], s[0][2], s[0][3], s[0][4], s[0][5]};
-    uint64_t c = sc[0];
-    for (int w = 1; w < kBlock / 64; ++w) {
-        for (int a = 0; a < 3; ++a) r[a] = fminf(r[a], s[w][a]);
-        for (int a = 3; a < 6; ++a) r[a] = fmaxf(r[a], s[w][a]);
-        c += sc[w];
-    }
+    const Frame &F0 = frames[0];
     P->n = n;
-    P->d = d;
-    P->d2 = __fmul_rn(d, d);
-    P->min_size = min_size < 1 ? 1 : min_size;
-    P->max_size = max_size;
-    P->status = kStatusOk;
-    P->nvalid = (int64_t)c;
+    P->nframes = nframes;
+    P->d = F0.d;
+    P->d2 = F0.d2;
+    P->min_size = F0.min_size;
+    P->max_size = F0.max_size;
+    P->status = s_bad ? kStatusInval : kStatusOk;
+    P->nvalid = nvalid;
     P->kept = 0;
     P->M = 0;
     P->Mcol = 0;
     P->max_cell = 0;
-
-    const double side = (double)d * (1.0 - 0x1p-10) / sqrt(3.0);
-    const double inv = 1.0 / side;
-    P->inv_s = inv;
-    int64_t N3[3] = {1, 1, 1};
-    double o3[3] = {0.0, 0.0, 0.0};
-    if (c > 0) {
-        for (int a = 0; a < 3; ++a) {
-            o3[a] = (double)r[a];
-            const double ext = ((double)r[a + 3] - (double)r[a]) * inv;
-            if (!(ext < 0x1p31)) {
-                P->status = kStatusRange;
-            } else {
-                N3[a] = (int64_t)floor(ext) + 1;
-            }
-        }
-    }
-    P->ox = o3[0]; P->oy = o3[1]; P->oz = o3[2];
-    P->NX = N3[0]; P->NY = N3[1]; P->NZ = N3[2];
-    P->NYp = (N3[1] + 31) / 32 * 32;
-    P->bx = bits_for(N3[0]);
-    P->by = bits_for(N3[1]);
-    P->bz = bits_for(N3[2]);
+    P->inv_s = F0.inv_s;
+    P->ox = F0.ox; P->oy = F0.oy; P->oz = F0.oz;
+    const int64_t NX = carry - 2;  // no gap after the last frame
+    P->NX = NX; P->NY = NY; P->NZ = NZ;
+    P->NYp = (NY + 31) / 32 * 32;
+    P->bx = bits_for(NX);
+    P->by = bits_for(NY);
+    P->bz = bits_for(NZ);
     P->giant = -1;
     P->nwork = 0;
-    P->dense_cols = ((double)N3[0] * (double)P->NYp <= (double)colgrid_cap) ? 1 : 0;
+    P->dense_cols = ((double)NX * (double)P->NYp <= (double)colgrid_cap) ? 1 : 0;
     const int B = P->bx + P->by + P->bz;
-    const int kb = B + (((int64_t)c < n) ? 1 : 0);
+    const int kb = B + ((nvalid < n) ? 1 : 0);
     int ib = bits_for(n);
     if (ib < 1) ib = 1;
     P->key_bits = kb;
@@ -254,7 +367,8 @@ __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ parti
     // separate key and index arrays; beyond a 64-bit key the grid is refused.
     P->pair_mode = (kb + ib > 64) ? 1 : 0;
     P->key_shift = P->pair_mode ? 0 : ib;
-    if (kb > 64) P->status = kStatusRange;
+    if (kb > 64 && P->status == kStatusOk) P->status = kStatusRange;
+    if (nframes == 1 && F0.status != kStatusOk && P->status == kStatusOk) P->status = F0.status;
     P->npasses = P->status == kStatusOk ? (kb + kRadixBits - 1) / kRadixBits : 0;
 }
 
@@ -266,37 +380,43 @@ __device__ __forceinline__ uint64_t make_key(uint64_t cx, uint64_t cy, uint64_t 
 }
 
 // ------------------------------------------------------------- 3. keys
-// Packs (cell key << idx_bits) | point index, counts the radix digits of
-// every pass, and clears the first look-back buffer.
+// Packs (cell key << idx_bits) | point index and counts the radix digits of
+// every pass.  Block f * per_frame + j takes the j-th share of frame f; the
+// cell's x coordinate is offset by the frame's place in the stacked grid.
+// Points of a refused frame get the key of non-finite points (sorted last).
 __global__ __launch_bounds__(kBlock) void k_keys(const float *__restrict__ xyz,
                                                  Params *__restrict__ P,
+                                                 const Frame *__restrict__ frames, int per_frame,
                                                  uint64_t *__restrict__ keys,
                                                  uint32_t *__restrict__ vals) {
     __shared__ uint32_t sh[kMaxPasses][kRadix];
     if (P->status != kStatusOk) return;
     for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kBlock) (&sh[0][0])[i] = 0;
     __syncthreads();
-    const int64_t n = P->n;
+    const int f = blockIdx.x / per_frame, j = blockIdx.x % per_frame;
+    const Frame *F = frames + f;
+    const int64_t lo = F->off0, hi = F->off1;
+    const bool accepted = F->status == kStatusOk;
     const int np = P->npasses;
     const int ks = P->key_shift;
     const bool pair = P->pair_mode != 0;
-    const double ox = P->ox, oy = P->oy, oz = P->oz, inv = P->inv_s;
-    const int64_t NX = P->NX, NY = P->NY, NZ = P->NZ;
+    const double ox = F->ox, oy = F->oy, oz = F->oz, inv = F->inv_s;
+    const int64_t NX = F->NX, NY = F->NY, NZ = F->NZ, xoff = F->xoff;
     const int by = P->by, bz = P->bz;
     const uint64_t invalid_key = 1ull << (P->bx + by + bz);
     const int lane = __lane_id();
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
+    for (int64_t i = lo + (int64_t)j * kBlock + threadIdx.x; i < hi;
+         i += (int64_t)per_frame * kBlock) {
         const float x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
         uint64_t key;
-        if (finite3(x, y, z)) {
+        if (accepted && finite3(x, y, z)) {
             int64_t cx = (int64_t)floor(((double)x - ox) * inv);
             int64_t cy = (int64_t)floor(((double)y - oy) * inv);
             int64_t cz = (int64_t)floor(((double)z - oz) * inv);
             cx = cx < 0 ? 0 : (cx >= NX ? NX - 1 : cx);
             cy = cy < 0 ? 0 : (cy >= NY ? NY - 1 : cy);
             cz = cz < 0 ? 0 : (cz >= NZ ? NZ - 1 : cz);
-            key = make_key((uint64_t)cx, (uint64_t)cy, (uint64_t)cz, by, bz);
+            key = make_key((uint64_t)(xoff + cx), (uint64_t)cy, (uint64_t)cz, by, bz);
         } else {
             key = invalid_key;
         }
@@ -628,6 +748,29 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const uint32_t *__restrict__
     }
 }
 
+// Frame whose stacked x range holds cell column cx: the last frame with
+// xoff <= cx (frames are stacked in order, so xoff increases).
+__device__ __forceinline__ int frame_of_x(const Frame *frames, int nframes, int64_t cx) {
+    int lo = 0, hi = nframes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (frames[mid].xoff <= cx) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Frame holding original point index i: the last frame with off0 <= i.
+__device__ __forceinline__ int frame_of_point(const Frame *frames, int nframes, int64_t i) {
+    int lo = 0, hi = nframes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (frames[mid].off0 <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // ------------------------------------------------------------- 7. cells
 // Cell table (first sorted position and key of every occupied cell) and
 // column table (key and first cell of every occupied column (cx, cy)), plus
@@ -642,11 +785,14 @@ __global__ __launch_bounds__(kBlock) void k_cells(const uint64_t *__restrict__ s
                                                   uint32_t *__restrict__ col_cell,
                                                   int32_t *__restrict__ cpar,
                                                   uint32_t *__restrict__ csize,
-                                                  uint32_t *__restrict__ ccanon) {
+                                                  uint32_t *__restrict__ ccanon,
+                                                  Frame *__restrict__ frames,
+                                                  uint32_t *__restrict__ cell_frame) {
     if (P->status != kStatusOk) return;
     const uint64_t *srt = (P->npasses & 1) ? s1 : s0;
     const int64_t nvalid = P->nvalid;
-    const int ks = P->key_shift, bz = P->bz;
+    const int ks = P->key_shift, bz = P->bz, xshift = P->by + P->bz;
+    const int nframes = P->nframes;
     const int64_t base = (int64_t)blockIdx.x * kTile;
     const int wave = threadIdx.x >> 6, lane = __lane_id();
     __shared__ uint32_t s_tot[2][kItems][kBlock / 64];
@@ -694,6 +840,13 @@ __global__ __launch_bounds__(kBlock) void k_cells(const uint64_t *__restrict__ s
             if (cf) {
                 col_key[colx] = key >> bz;
                 col_cell[colx] = cid;
+            }
+            if (nframes > 1) {  // the cell's frame; the frame's first cell
+                const int64_t cx = (int64_t)(key >> xshift);
+                const int fr = frame_of_x(frames, nframes, cx);
+                cell_frame[cid] = (uint32_t)fr;
+                if (cid == 0 || (int64_t)((srt[e - 1] >> ks) >> xshift) < frames[fr].xoff)
+                    frames[fr].cell0 = cid;
             }
         }
     }
@@ -900,12 +1053,15 @@ __global__ __launch_bounds__(kBlock) void k_runs1(const float4 *__restrict__ spt
                                                   const uint64_t *__restrict__ cell_key,
                                                   uint8_t *__restrict__ heads,
                                                   int32_t *__restrict__ blkhead,
+                                                  const Frame *__restrict__ frames,
+                                                  const uint32_t *__restrict__ cell_frame,
                                                   const Params *__restrict__ P) {
     if (P->status != kStatusOk) return;
     const int64_t M = P->M;
     const int64_t base = (int64_t)blockIdx.x * kTile;
     if (base >= M) return;
-    const float d2 = P->d2;
+    const float d2_one = P->d2;
+    const bool batched = P->nframes > 1;
     const Grid g = grid_of(P);
     int32_t last = -1;
     for (int k = 0; k < kItems; ++k) {
@@ -914,9 +1070,11 @@ __global__ __launch_bounds__(kBlock) void k_runs1(const float4 *__restrict__ spt
         bool head = true;
         if (A > 0) {
             const uint64_t kp = cell_key[A - 1], ka = cell_key[A];
-            if (next_is_near(g, kp, ka))
+            if (next_is_near(g, kp, ka)) {  // same x, so the same frame
+                const float d2 = batched ? frames[cell_frame[A]].d2 : d2_one;
                 head = !any_joined(spts, cell_start[A - 1], cell_start[A], cell_start[A],
                                    cell_start[A + 1], d2);
+            }
         }
         heads[A] = head ? 1 : 0;
         if (head) last = (int32_t)A;
@@ -1014,11 +1172,14 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
                                                       const uint32_t *__restrict__ col_cell,
                                                       const uint32_t *__restrict__ colgrid,
                                                       const uint32_t *__restrict__ colbits,
+                                                      const Frame *__restrict__ frames,
+                                                      const uint32_t *__restrict__ cell_frame,
                                                       int32_t *cpar, const Params *__restrict__ P) {
     if (P->status != kStatusOk) return;
     const int64_t M = P->M, Mcol = P->Mcol;
     const int dense = P->dense_cols;
-    const float d2 = P->d2;
+    const float d2_one = P->d2;
+    const bool batched = P->nframes > 1;
     const Grid g = grid_of(P);
     constexpr int kC = 4;
     constexpr int kCand = kC * kNearK + 1;
@@ -1030,6 +1191,7 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
         const uint64_t kup = A + 1 < M ? cell_key[A + 1] : ~0ull;
         const uint32_t sA = cell_start[A], eA = cell_start[A + 1];
         const int32_t p0 = cpar[A];
+        const uint32_t fA = batched ? cell_frame[A] : 0u;
         const uint64_t ck = key >> g.bz;
         const int64_t cz = (int64_t)(key & g.zmask);
         int64_t cx, cy;
@@ -1094,6 +1256,7 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
             eb[i] = c ? cell_start[B + 1] : 0u;
         }
         int32_t ra = (q0 == p0) ? p0 : uf_find(cpar, q0);
+        const float d2 = batched ? frames[fA].d2 : d2_one;  // neighbours share A's frame
         FEC_COUNT(P, 0, __popc(cm));
         // round 5: the first point of every candidate in another component,
         // tested against A's first point all at once; that one pair decides
@@ -1150,25 +1313,43 @@ __global__ __launch_bounds__(kBlock) void k_compress(int32_t *cpar, const Params
     }
 }
 
-// The most frequent root among up to 4096 evenly spaced cells.  One block.
+// The most frequent root among up to 4096 evenly spaced cells of one frame.
+// One block per frame.
 constexpr int kGiantSample = 4096;
 constexpr int kGiantSlots = 8192;
 
 __global__ __launch_bounds__(1024) void k_giant(const int32_t *__restrict__ cpar,
+                                                Frame *__restrict__ frames,
                                                 Params *__restrict__ P) {
     if (P->status != kStatusOk) return;
     __shared__ int32_t t_key[kGiantSlots];
     __shared__ uint32_t t_cnt[kGiantSlots];
     __shared__ uint64_t s_best[1024 / 64];
-    const int64_t M = P->M;
+    const int nframes = P->nframes;
+    const int f = blockIdx.x;
+    // the frame's cells: from its first cell to the next non-empty frame's
+    int64_t c0 = 0, c1 = P->M;
+    if (nframes > 1) {
+        if (frames[f].nvalid == 0) {
+            if (threadIdx.x == 0) frames[f].giant = -1;
+            return;
+        }
+        c0 = frames[f].cell0;
+        for (int g = f + 1; g < nframes; ++g)
+            if (frames[g].nvalid > 0) {
+                c1 = frames[g].cell0;
+                break;
+            }
+    }
+    const int64_t Mf = c1 - c0;
     for (int i = threadIdx.x; i < kGiantSlots; i += 1024) {
         t_key[i] = -1;
         t_cnt[i] = 0;
     }
     __syncthreads();
-    const int64_t S = M < kGiantSample ? M : kGiantSample;
+    const int64_t S = Mf < kGiantSample ? Mf : kGiantSample;
     for (int64_t i = threadIdx.x; i < S; i += 1024) {
-        const int32_t r = cpar[i * M / S];
+        const int32_t r = cpar[c0 + i * Mf / S];
         uint32_t h = ((uint32_t)r * 2654435761u) >> (32 - 13);
         for (int probe = 0; probe < kGiantSlots; ++probe) {
             const int32_t prev = atomicCAS(&t_key[h], -1, r);
@@ -1199,8 +1380,9 @@ __global__ __launch_bounds__(1024) void k_giant(const int32_t *__restrict__ cpar
     if (threadIdx.x == 0) {
         uint64_t b = 0;
         for (int w = 0; w < 1024 / 64; ++w) b = s_best[w] > b ? s_best[w] : b;
-        P->giant = b ? (int32_t)(0x7FFFFFFFu - (uint32_t)(b & 0xFFFFFFFFu)) : -1;
-        P->nwork = 0;
+        const int32_t giant = b ? (int32_t)(0x7FFFFFFFu - (uint32_t)(b & 0xFFFFFFFFu)) : -1;
+        frames[f].giant = giant;
+        if (nframes == 1) P->giant = giant;
     }
 }
 
@@ -1212,12 +1394,20 @@ __global__ __launch_bounds__(1024) void k_giant(const int32_t *__restrict__ cpar
 __global__ __launch_bounds__(kBlock) void k_nongiant(const int32_t *__restrict__ cpar,
                                                      uint64_t *__restrict__ gbits,
                                                      uint32_t *__restrict__ work,
+                                                     const Frame *__restrict__ frames,
+                                                     const uint32_t *__restrict__ cell_frame,
                                                      Params *__restrict__ P) {
     if (P->status != kStatusOk) return;
     __shared__ uint32_t s_wcnt[kBlock / 64];
     __shared__ uint32_t s_base;
     const int64_t M = P->M;
-    const int32_t giant = P->giant;
+    const bool batched = P->nframes > 1;
+    const int32_t giant_one = P->giant;
+    // in the giant component of its frame
+    auto in_giant = [&](int64_t A) {
+        const int32_t gA = batched ? frames[cell_frame[A]].giant : giant_one;
+        return cpar[A] == gA;
+    };
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     // chunk of whole 256-cell groups (keeps the bitmap words aligned)
     const int64_t groups = (M + kBlock - 1) / kBlock;
@@ -1229,7 +1419,7 @@ __global__ __launch_bounds__(kBlock) void k_nongiant(const int32_t *__restrict__
     for (int64_t b0 = c0; b0 < c1; b0 += kBlock) {
         const int64_t A = b0 + threadIdx.x;
         const bool valid = A < c1;
-        const bool gi = valid && cpar[A] == giant;
+        const bool gi = valid && in_giant(A);
         const uint64_t gm = __ballot(gi);
         if (lane == 0 && valid) gbits[A >> 6] = gm;  // A is 64-aligned on lane 0
         mine += (valid && !gi) ? 1u : 0u;
@@ -1247,7 +1437,7 @@ __global__ __launch_bounds__(kBlock) void k_nongiant(const int32_t *__restrict__
     for (int64_t b0 = c0; b0 < c1; b0 += kBlock) {
         const int64_t A = b0 + threadIdx.x;
         const bool valid = A < c1;
-        const bool w = valid && cpar[A] != giant;
+        const bool w = valid && !in_giant(A);
         const uint64_t wm = __ballot(w);
         if (lane == 0) s_wcnt[wave] = (uint32_t)__popcll(wm);
         __syncthreads();
@@ -1282,12 +1472,15 @@ __global__ __launch_bounds__(kBlock) void k_hook_far(const float4 *__restrict__ 
                                                       const uint32_t *__restrict__ colbits,
                                                       const uint64_t *__restrict__ gbits,
                                                       const uint32_t *__restrict__ work,
+                                                      const Frame *__restrict__ frames,
+                                                      const uint32_t *__restrict__ cell_frame,
                                                       int32_t *cpar, const Params *__restrict__ P) {
     if (P->status != kStatusOk) return;
     const int64_t M = P->M, Mcol = P->Mcol;
     const uint32_t nwork = P->nwork;
     const int dense = P->dense_cols;
-    const float d2 = P->d2;
+    const float d2_one = P->d2;
+    const bool batched = P->nframes > 1;
     const Grid g = grid_of(P);
     constexpr int kG = 8;      // columns per group (loads issued together)
     constexpr int kK = 2;      // cells per column loaded up front
@@ -1300,6 +1493,7 @@ __global__ __launch_bounds__(kBlock) void k_hook_far(const float4 *__restrict__ 
         g.col_xy(ck, cx, cy);
         const uint32_t sA = cell_start[A], eA = cell_start[A + 1];
         int32_t ra = uf_find(cpar, A);
+        const float d2 = batched ? frames[cell_frame[A]].d2 : d2_one;
         auto pair = [&](uint32_t B, int32_t rb) {
             FEC_COUNT(P, 5, 1);
             if (rb == ra) return;
@@ -1489,42 +1683,86 @@ __global__ __launch_bounds__(kBlock) void k_final_cells(const int32_t *__restric
     if (threadIdx.x == 0) atomicMax(&P->max_cell, (int32_t)s_max);
 }
 
-// Labels in the caller's order and the number of kept clusters.
+// Labels in the caller's order and the number of kept clusters.  With
+// several frames, each cell takes its frame's size bounds, its label counts
+// from the frame's first point, and kept clusters are counted per frame.
 __global__ __launch_bounds__(kBlock) void k_final_labels(const int32_t *__restrict__ cpar,
                                                          const uint32_t *__restrict__ cell_start,
                                                          const uint32_t *__restrict__ sorig,
                                                          const uint32_t *__restrict__ csize,
                                                          const uint32_t *__restrict__ ccanon,
                                                          int32_t *__restrict__ labels,
+                                                         Frame *__restrict__ frames,
+                                                         const uint32_t *__restrict__ cell_frame,
                                                          Params *__restrict__ P) {
     if (P->status != kStatusOk) return;
     const int64_t M = P->M;
-    const uint32_t lo = (uint32_t)P->min_size, hi = (uint32_t)P->max_size;
+    const int nframes = P->nframes;
+    const bool batched = nframes > 1;
+    const int lane = __lane_id();
     uint32_t kept = 0;
+    const uint32_t lo_one = (uint32_t)P->min_size, hi_one = (uint32_t)P->max_size;
     for (int64_t A = (int64_t)blockIdx.x * kBlock + threadIdx.x; A < M;
          A += (int64_t)gridDim.x * kBlock) {
+        uint32_t lo = lo_one, hi = hi_one;
+        int32_t base = 0;
+        uint32_t f = 0;
+        if (batched) {
+            f = cell_frame[A];
+            lo = (uint32_t)frames[f].min_size;
+            hi = (uint32_t)frames[f].max_size;
+            base = (int32_t)frames[f].off0;
+        }
         const int32_t r = cpar[A];
         const uint32_t sz = csize[r];
         const bool ok = sz >= lo && sz <= hi;
-        const int32_t lab = ok ? (int32_t)ccanon[r] : -1;
-        kept += (ok && r == (int32_t)A) ? 1u : 0u;
+        const int32_t lab = ok ? (int32_t)ccanon[r] - base : -1;
+        const bool root_kept = ok && r == (int32_t)A;
+        if (!batched) {
+            kept += root_kept ? 1u : 0u;
+        } else {
+            // one atomic per wave when the wave's kept roots share a frame
+            const uint64_t km = __ballot(root_kept);
+            if (km) {
+                const uint32_t f0 = __shfl(f, first_lane(km));
+                if (__ballot(root_kept && f == f0) == km) {
+                    if (lane == first_lane(km)) atomicAdd(&frames[f0].kept, (int32_t)__popcll(km));
+                } else if (root_kept) {
+                    atomicAdd(&frames[f].kept, 1);
+                }
+            }
+        }
         const uint32_t s = cell_start[A], e = cell_start[A + 1];
         for (uint32_t p = s; p < e; ++p) labels[sorig[p]] = lab;
     }
-    // non-finite points (sorted after every finite one): singletons
+    // points sorted after every cell (non-finite, or of a refused frame):
+    // singletons
     const int64_t n = P->n, nvalid = P->nvalid;
-    const bool one_ok = lo <= 1u && 1u <= hi;
     for (int64_t p = nvalid + (int64_t)blockIdx.x * kBlock + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * kBlock) {
         const uint32_t o = sorig[p];
-        labels[o] = one_ok ? (int32_t)o : -1;
-        kept += one_ok ? 1u : 0u;
+        uint32_t lo = lo_one, hi = hi_one;
+        int32_t base = 0;
+        int f = 0;
+        bool accepted = true;
+        if (batched) {
+            f = frame_of_point(frames, nframes, (int64_t)o);
+            lo = (uint32_t)frames[f].min_size;
+            hi = (uint32_t)frames[f].max_size;
+            base = (int32_t)frames[f].off0;
+            accepted = frames[f].status == kStatusOk;
+        }
+        const bool one_ok = accepted && lo <= 1u && 1u <= hi;
+        labels[o] = one_ok ? (int32_t)o - base : -1;
+        if (!batched) kept += one_ok ? 1u : 0u;
+        else if (one_ok) atomicAdd(&frames[f].kept, 1);
     }
+    if (batched) return;
     kept = wave_sum(kept);
     __shared__ uint32_t s_k;
     if (threadIdx.x == 0) s_k = 0;
     __syncthreads();
-    if (__lane_id() == 0 && kept) atomicAdd(&s_k, kept);
+    if (lane == 0 && kept) atomicAdd(&s_k, kept);
     __syncthreads();
     if (threadIdx.x == 0 && s_k) atomicAdd(&P->kept, (int32_t)s_k);
 }
@@ -1538,8 +1776,18 @@ __global__ __launch_bounds__(kBlock) void k_error_fill(int32_t *__restrict__ lab
         labels[i] = -1;
 }
 
-__global__ void k_finish(const Params *__restrict__ P, int32_t *__restrict__ k_out) {
-    if (k_out) *k_out = P->status != kStatusOk ? P->status : P->kept;
+// Per frame: kept clusters, or the frame's (else the call's) failure status.
+__global__ __launch_bounds__(kBlock) void k_finish(const Params *__restrict__ P,
+                                                   const Frame *__restrict__ frames, int nframes,
+                                                   int32_t *__restrict__ k_out) {
+    if (!k_out) return;
+    for (int f = blockIdx.x * kBlock + threadIdx.x; f < nframes; f += gridDim.x * kBlock) {
+        int32_t v;
+        if (P->status != kStatusOk) v = P->status;
+        else if (nframes == 1) v = P->kept;
+        else v = frames[f].status != kStatusOk ? frames[f].status : frames[f].kept;
+        k_out[f] = v;
+    }
 }
 
 // ------------------------------------------------------------------ host side
@@ -1553,11 +1801,15 @@ const char *stage_name(int s) {
     return (s >= 0 && s < kNumStages) ? names[s] : "";
 }
 
-hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_size,
-                           int32_t max_size, int32_t *labels_out, int32_t *k_out, void *ws,
-                           const Layout &L, hipStream_t st, Timer *timer) {
+hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipStream_t st,
+                           Timer *timer) {
+    const float *xyz = args.xyz;
+    const int64_t n = args.n;
+    const int nframes = args.nframes;
+    int32_t *labels_out = args.labels_out;
     char *w = static_cast<char *>(ws);
     Params *P = reinterpret_cast<Params *>(w + L.params);
+    Frame *frames = reinterpret_cast<Frame *>(w + L.frames);
     float *partials = reinterpret_cast<float *>(w + L.partials);
     uint32_t *tile_cnt = reinterpret_cast<uint32_t *>(w + L.tile_cnt);
     uint32_t *tile_off = reinterpret_cast<uint32_t *>(w + L.tile_off);
@@ -1581,13 +1833,17 @@ hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_siz
     int32_t *blkhead = reinterpret_cast<int32_t *>(w + L.blkhead);
     uint64_t *gbits = reinterpret_cast<uint64_t *>(w + L.gbits);
     uint32_t *work = reinterpret_cast<uint32_t *>(w + L.work);
+    uint32_t *cell_frame = nframes > 1 ? reinterpret_cast<uint32_t *>(w + L.cell_frame) : nullptr;
 
     const int64_t ntiles = L.ntiles;
-    int nb_bbox = (int)((n + kBlock * 4 - 1) / (kBlock * 4));
-    nb_bbox = nb_bbox < 1 ? 1 : (nb_bbox > kBboxBlocks ? kBboxBlocks : nb_bbox);
+    const int bbox_pf = L.bbox_per_frame;
     int64_t nb_pts = (n + kBlock - 1) / kBlock;
     const int nb_stream = (int)(nb_pts > 8192 ? 8192 : (nb_pts < 1 ? 1 : nb_pts));
     const int nb_cells = (int)(nb_pts > kCellBlocks ? kCellBlocks : (nb_pts < 1 ? 1 : nb_pts));
+    // key blocks per frame: about nb_stream in all, at least one per frame
+    int keys_pf = nb_stream / nframes;
+    keys_pf = keys_pf < 1 ? 1 : keys_pf;
+    const int nb_finish = (nframes + kBlock - 1) / kBlock;
     // Passes beyond the device-side count return at once; the pair-mode
     // fallback can need up to a full 64-bit key.
     const int max_passes = kMaxPasses;
@@ -1601,10 +1857,14 @@ hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_siz
         if (timer) timer->end(stage, st);              \
     } while (0)
 
-    FEC_LAUNCH(kStBbox, k_bbox<<<nb_bbox, kBlock, 0, st>>>(xyz, n, partials));
-    FEC_LAUNCH(kStPlan, k_plan<<<1, kBlock, 0, st>>>(partials, nb_bbox, P, n, d, min_size,
-                                                      max_size, L.colgrid_cap));
-    FEC_LAUNCH(kStKeys, k_keys<<<nb_stream, kBlock, 0, st>>>(xyz, P, keys0, vals0));
+    FEC_LAUNCH(kStBbox, k_bbox<<<(unsigned)(nframes * bbox_pf), kBlock, 0, st>>>(
+                            xyz, n, args.offsets, bbox_pf, partials));
+    FEC_LAUNCH(kStPlan, k_plan<<<1, kBlock, 0, st>>>(partials, bbox_pf, P, frames, nframes, n,
+                                                      args.offsets, args.d_arr, args.min_arr,
+                                                      args.max_arr, args.d, args.min_size,
+                                                      args.max_size, L.colgrid_cap));
+    FEC_LAUNCH(kStKeys, k_keys<<<(unsigned)(nframes * keys_pf), kBlock, 0, st>>>(
+                            xyz, P, frames, keys_pf, keys0, vals0));
     for (int pass = 0; pass < max_passes; ++pass) {
         const uint64_t *src = (pass & 1) ? keys1 : keys0;
         uint64_t *dst = (pass & 1) ? keys0 : keys1;
@@ -1622,29 +1882,32 @@ hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_siz
     FEC_LAUNCH(kStTileScan, k_tile_scan<<<1, 1024, 0, st>>>(tile_cnt, tile_off, ntiles, P));
     FEC_LAUNCH(kStCells, k_cells<<<(unsigned)ntiles, kBlock, 0, st>>>(
                              keys0, keys1, P, tile_off, cell_start, cell_key, col_key, col_cell,
-                             cpar, csize, ccanon));
+                             cpar, csize, ccanon, frames, cell_frame));
     FEC_LAUNCH(kStColGrid, k_colgrid<<<nb_cells, kBlock, 0, st>>>(col_key, col_cell, cell_start,
                                                                    colgrid, colbits, P));
     // runs, near shell, giant component, far shell
-    FEC_LAUNCH(kStRuns, k_runs1<<<(unsigned)ntiles, kBlock, 0, st>>>(spts, cell_start, cell_key,
-                                                                      heads, blkhead, P));
+    FEC_LAUNCH(kStRuns, k_runs1<<<(unsigned)ntiles, kBlock, 0, st>>>(
+                            spts, cell_start, cell_key, heads, blkhead, frames, cell_frame, P));
     FEC_LAUNCH(kStRuns, k_runs2<<<(unsigned)ntiles, kBlock, 0, st>>>(heads, blkhead, cpar, P));
     FEC_LAUNCH(kStHookNear, k_hook_near<<<nb_cells, kBlock, 0, st>>>(
                                 spts, cell_start, cell_key, col_key, col_cell, colgrid, colbits,
-                                cpar, P));
+                                frames, cell_frame, cpar, P));
     FEC_LAUNCH(kStCompress1, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P));
-    FEC_LAUNCH(kStGiant, k_giant<<<1, 1024, 0, st>>>(cpar, P));
-    FEC_LAUNCH(kStWorkList, k_nongiant<<<nb_cells, kBlock, 0, st>>>(cpar, gbits, work, P));
+    FEC_LAUNCH(kStGiant, k_giant<<<(unsigned)nframes, 1024, 0, st>>>(cpar, frames, P));
+    FEC_LAUNCH(kStWorkList, k_nongiant<<<nb_cells, kBlock, 0, st>>>(cpar, gbits, work, frames,
+                                                                     cell_frame, P));
     FEC_LAUNCH(kStHookFar, k_hook_far<<<nb_cells, kBlock, 0, st>>>(
                                 spts, cell_start, cell_key, col_key, col_cell, colgrid, colbits,
-                                gbits, work, cpar, P));
+                                gbits, work, frames, cell_frame, cpar, P));
     FEC_LAUNCH(kStCompress2, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P));
     FEC_LAUNCH(kStFinalCells, k_final_cells<<<nb_cells, kBlock, 0, st>>>(
                                   cpar, cell_start, sorig, csize, ccanon, P));
     FEC_LAUNCH(kStFinalLabels, k_final_labels<<<nb_cells, kBlock, 0, st>>>(
-                                   cpar, cell_start, sorig, csize, ccanon, labels_out, P));
+                                   cpar, cell_start, sorig, csize, ccanon, labels_out, frames,
+                                   cell_frame, P));
     FEC_LAUNCH(kStFinish, k_error_fill<<<nb_stream, kBlock, 0, st>>>(labels_out, n, P));
-    FEC_LAUNCH(kStFinish, k_finish<<<1, 1, 0, st>>>(P, k_out));
+    FEC_LAUNCH(kStFinish, k_finish<<<(unsigned)nb_finish, kBlock, 0, st>>>(P, frames, nframes,
+                                                                           args.k_out));
 #undef FEC_LAUNCH
     return hipSuccess;
 }

@@ -19,15 +19,41 @@ constexpr int kCellBlocks = 4096;      // grid of the grid-stride per-cell kerne
 // Dense column index: one entry per (cx, cy) when the plane has at most
 // kColGridPerPoint entries per point (else columns are binary-searched).
 constexpr int kColGridPerPoint = 8;
+// Frames of one batched call (each frame is an independent cloud).
+constexpr int32_t kMaxFrames = 65536;
 
 
 // Device-side status values (mirror the public FEC_* codes).
 constexpr int32_t kStatusOk = 0;
+constexpr int32_t kStatusInval = -1;
 constexpr int32_t kStatusRange = -2;
 constexpr int32_t kStatusDevice = -4;
 
+// One frame of a batched call.  Every frame has its own grid (its own d,
+// hence cell side, and its own bounding box); the grids are laid side by
+// side along x, frame after frame, with two empty cell columns between
+// consecutive frames, so the stencil (reach two cells) never joins cells of
+// different frames and one sorted key order covers the whole batch.
+struct Frame {
+    int64_t off0, off1;  // the frame's points [off0, off1) of the batch
+    int64_t nvalid;      // finite points (0 when the frame's arguments are refused)
+    int64_t xoff;        // first x cell of the frame in the stacked grid
+    double ox, oy, oz;   // grid origin: bounding box minimum of the finite points
+    double inv_s;        // 1 / cell side (0 for a refused frame)
+    int64_t NX, NY, NZ;  // the frame's own grid extent
+    float d, d2;         // threshold and fl32(d * d)
+    int32_t min_size;    // clamped to >= 1
+    int32_t max_size;
+    int32_t status;      // kStatusOk, kStatusInval (arguments) or kStatusRange (extent)
+    int32_t kept;        // kept clusters
+    int32_t giant;       // root of the frame's largest component after sampling (-1: none)
+    uint32_t cell0;      // the frame's first cell (when nvalid > 0)
+};
+
 // Per-call state, kept at the start of the workspace.  Written by the
-// planning kernel, read by every later kernel of the call.
+// planning kernel, read by every later kernel of the call.  With several
+// frames the grid fields describe the stacked grid; d, d2, origin and the
+// size bounds are those of frame 0 (the only frame of a single-cloud call).
 struct Params {
     int64_t n;
     float d;
@@ -35,8 +61,8 @@ struct Params {
     int32_t min_size;  // already clamped to >= 1
     int32_t max_size;
     int32_t status;
-    int32_t pad0;
-    int64_t nvalid;    // points with three finite coordinates
+    int32_t nframes;
+    int64_t nvalid;    // points with three finite coordinates (of accepted frames)
     double ox, oy, oz; // grid origin: the bounding box minimum of finite points
     double inv_s;      // 1 / cell side
     int64_t NX, NY, NZ;
@@ -62,13 +88,15 @@ struct Params {
 
 // ---------------------------------------------------------------- workspace
 struct Layout {
-    size_t params, partials, tile_cnt, tile_off;
+    size_t params, frames, partials, tile_cnt, tile_off;
     size_t keys0, keys1, vals0, vals1, th;
     size_t spts, sorig, cell_start, cell_key, cpar, csize, ccanon;
-    size_t col_key, col_cell, colgrid, colbits, heads, blkhead, gbits, work;
+    size_t col_key, col_cell, colgrid, colbits, heads, blkhead, gbits, work, cell_frame;
     uint64_t colgrid_cap;
     size_t total;
     int64_t ntiles;
+    int32_t nframes;
+    int32_t bbox_per_frame;  // blocks of the bounding-box reduction per frame
 };
 
 inline uint64_t next_pow2(uint64_t v) {
@@ -79,8 +107,20 @@ inline uint64_t next_pow2(uint64_t v) {
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-inline Layout make_layout(int64_t n) {
+// Bounding-box blocks per frame: about kBboxBlocks in all, at most one per
+// 1024 points of an average frame, at least one.
+inline int32_t bbox_blocks_per_frame(int64_t n, int32_t nframes) {
+    const int64_t f = nframes > 0 ? nframes : 1;
+    int64_t b = kBboxBlocks / f;
+    const int64_t need = (n / f + 1023) / 1024;
+    if (b > need) b = need;
+    return (int32_t)(b < 1 ? 1 : b);
+}
+
+inline Layout make_layout(int64_t n, int32_t nframes = 1) {
     Layout L{};
+    L.nframes = nframes;
+    L.bbox_per_frame = bbox_blocks_per_frame(n, nframes);
     const size_t A = 256;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -91,7 +131,8 @@ inline Layout make_layout(int64_t n) {
     const size_t un = (size_t)(n > 0 ? n : 1);
     L.ntiles = (int64_t)((un + kTile - 1) / kTile);
     L.params = take(sizeof(Params));
-    L.partials = take((size_t)kBboxBlocks * 8 * sizeof(float));
+    L.frames = take((size_t)nframes * sizeof(Frame));
+    L.partials = take((size_t)nframes * L.bbox_per_frame * 8 * sizeof(float));
     L.tile_cnt = take((size_t)L.ntiles * 2 * sizeof(uint32_t));
     L.tile_off = take((size_t)L.ntiles * 2 * sizeof(uint32_t));
     L.keys0 = take(un * sizeof(uint64_t));
@@ -115,6 +156,7 @@ inline Layout make_layout(int64_t n) {
     L.blkhead = take((size_t)L.ntiles * sizeof(int32_t));
     L.gbits = take((un / 64 + 1) * sizeof(uint64_t));
     L.work = take(un * sizeof(uint32_t));
+    L.cell_frame = take(nframes > 1 ? un * sizeof(uint32_t) : 0);  // frame of every cell
     L.total = off;
     return L;
 }
@@ -153,9 +195,27 @@ struct Timer {
     virtual ~Timer() {}
 };
 
+// Arguments of one call: a single cloud (nframes == 1, the scalars d,
+// min_size, max_size; offsets and the per-frame arrays null) or a batch of
+// frames (device arrays offsets[nframes + 1], d[nframes], min_size[nframes],
+// max_size[nframes]).  Labels are frame-local: the smallest index of the
+// cluster counted from the frame's first point.  k_out holds one value per
+// frame.
+struct CallArgs {
+    const float *xyz;
+    int64_t n;
+    int32_t nframes;
+    const int64_t *offsets;
+    const float *d_arr;
+    const int32_t *min_arr, *max_arr;
+    float d;
+    int32_t min_size, max_size;
+    int32_t *labels_out;
+    int32_t *k_out;
+};
+
 // Enqueues the whole pipeline.  Returns hipSuccess or the first launch error.
-hipError_t launch_pipeline(const float *xyz, int64_t n, float d, int32_t min_size,
-                           int32_t max_size, int32_t *labels_out, int32_t *k_out, void *ws,
-                           const Layout &L, hipStream_t stream, Timer *timer);
+hipError_t launch_pipeline(const CallArgs &a, void *ws, const Layout &L, hipStream_t stream,
+                           Timer *timer);
 
 }  // namespace fec

@@ -15,6 +15,8 @@ from .clouds import (  # noqa: F401
     near_threshold_cloud,
     chain_cloud,
     blob_lattice,
+    lidar_batch,
+    make_batch_config,
     CONFIGS,
     make_config,
 )

@@ -481,6 +481,21 @@ def near_threshold_cloud(n_pairs: int, d: float, seed: int = 0, max_ulps: int = 
     return out
 
 
+def lidar_batch(n_frames: int = 64, n_lo: int = 20000, n_hi: int = 200000,
+                ds=(0.2, 0.35, 0.5), seed: int = 4):
+    """Independent LiDAR frames for a batched call: (list of xyz, list of d).
+
+    Frame b has round(exp(U[ln n_lo, ln n_hi])) points (log-uniform count),
+    its own scene seed, and d drawn uniformly from ``ds``.
+    """
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0x6261]))
+    counts = np.rint(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), n_frames))).astype(np.int64)
+    dsel = rng.integers(0, len(ds), n_frames)
+    seeds = rng.integers(0, 2**31 - 1, n_frames)
+    frames = [lidar_frame(n=int(counts[b]), seed=int(seeds[b])) for b in range(n_frames)]
+    return frames, [float(ds[int(k)]) for k in dsel]
+
+
 # --------------------------------------------------------------------------
 # named configurations
 # --------------------------------------------------------------------------
@@ -490,6 +505,9 @@ CONFIGS = {
     "lidar120k": dict(kind="frame", n=120000, d=0.35, min_size=50, max_size=100000, seed=2),
     "map27m": dict(kind="map", n=27000000, d=0.2, min_size=100, max_size=5000000, seed=3,
                    n_frames=200, pts_per_frame=135000),
+    # batched frames: lidar_batch(64 frames, 20k-200k points, d in {0.2, 0.35, 0.5})
+    "batch64": dict(kind="batch", n_frames=64, n_lo=20000, n_hi=200000, min_size=30,
+                    max_size=200000, seed=4),
 }
 
 
@@ -501,6 +519,8 @@ def make_config(name: str, frames=None, **kw):
     """
     c = dict(CONFIGS[name])
     c.update(kw)
+    if c["kind"] == "batch":
+        raise ValueError("%s is a batch of frames: use make_batch_config" % name)
     if c["kind"] == "blobs":
         xyz = blobs_cloud(n=c["n"], seed=c["seed"])
     elif c["kind"] == "frame":
@@ -511,3 +531,12 @@ def make_config(name: str, frames=None, **kw):
         xyz = lidar_map(n_frames=c["n_frames"], pts_per_frame=c["pts_per_frame"],
                         seed=c["seed"], frames=frames)
     return xyz, float(c["d"]), int(c["min_size"]), int(c["max_size"])
+
+
+def make_batch_config(name: str = "batch64", **kw):
+    """(list of xyz, list of d, min_size, max_size) for a named batch workload."""
+    c = dict(CONFIGS[name])
+    c.update(kw)
+    frames, ds = lidar_batch(n_frames=c["n_frames"], n_lo=c["n_lo"], n_hi=c["n_hi"],
+                             seed=c["seed"])
+    return frames, ds, int(c["min_size"]), int(c["max_size"])

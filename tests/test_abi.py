@@ -81,3 +81,40 @@ def test_cpu_tensors_are_refused(fec):
     import torch
     with pytest.raises(ValueError):
         fec.cluster(torch.zeros((4, 3)), 0.5)
+
+
+def test_batch_host_side_argument_checks(fec):
+    lib = fec.raw_lib()
+    buf = ctypes.c_void_p(0x1000)   # never dereferenced: checks fail first
+    ws = ctypes.c_void_p(0x100000)
+    big = 1 << 40
+
+    def call(xyz, n, nf, offs, d, lo, hi, labels, k, w, wb):
+        return lib.fec_cluster_batch_async(xyz, n, nf, offs, d, lo, hi, labels, k, w, wb, None)
+
+    assert call(buf, -1, 2, buf, buf, buf, buf, buf, buf, ws, big) == fec.FEC_EINVAL
+    assert call(buf, 2**31, 2, buf, buf, buf, buf, buf, buf, ws, big) == fec.FEC_EINVAL
+    assert call(buf, 10, 0, buf, buf, buf, buf, buf, buf, ws, big) == fec.FEC_EINVAL
+    assert call(buf, 10, 65537, buf, buf, buf, buf, buf, buf, ws, big) == fec.FEC_EINVAL
+    for miss in range(5):   # offsets, d, min_size, max_size, k_out
+        a = [buf] * 5
+        a[miss] = None
+        assert call(buf, 10, 2, a[0], a[1], a[2], a[3], buf, a[4], ws, big) == fec.FEC_EINVAL
+    assert call(None, 10, 2, buf, buf, buf, buf, buf, buf, ws, big) == fec.FEC_EINVAL
+    assert call(buf, 10, 2, buf, buf, buf, buf, None, buf, ws, big) == fec.FEC_EINVAL
+    assert call(buf, 10, 2, buf, buf, buf, buf, buf, buf, ws, 16) == fec.FEC_EINVAL
+    assert call(buf, 10, 2, buf, buf, buf, buf, buf, buf, ctypes.c_void_p(0x100001),
+                big) == fec.FEC_EINVAL
+    assert lib.fec_last_error()
+
+
+def test_batch_workspace_bytes(fec):
+    assert fec.batch_workspace_bytes(1000, 0) == 0
+    assert fec.batch_workspace_bytes(-1, 3) == 0
+    a = fec.batch_workspace_bytes(1_000_000, 1)
+    b = fec.batch_workspace_bytes(1_000_000, 64)
+    # one frame: the single-cloud layout; frames add a frame table and a
+    # frame id per cell
+    assert a == fec.workspace_bytes(1_000_000)
+    assert a < b < a + 8 * 1_000_000
+    assert fec.batch_workspace_bytes(0, 5) > 0
