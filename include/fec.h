@@ -153,8 +153,12 @@ const char *fec_version(void);
  * cells along x, y, z, out[9] largest points per cell, out[10] status,
  * out[11] cells left outside the largest component after the near shell,
  * out[12] that component's root cell, out[13..20] diagnostic event counts
- * (zero unless the library was built with FEC_COUNTERS defined).
- * Writes min(max_out, 21) values; returns that count or a negative status.
+ * (zero unless the library was built with FEC_COUNTERS defined), out[21]
+ * the column index used (0 binary search, 1 dense table, 2 hash table).
+ * For a batched call the grid fields describe the frames' stacked grid,
+ * out[11] counts the cells outside each frame's largest component and
+ * out[12] is -1.
+ * Writes min(max_out, 22) values; returns that count or a negative status.
  */
 int32_t fec_workspace_stats(const void *workspace, void *stream, int64_t *out, int32_t max_out);
 

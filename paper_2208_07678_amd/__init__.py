@@ -90,7 +90,8 @@ EXPORTED = [
 
 STATS_FIELDS = ["n", "finite_points", "cells", "columns", "key_bits", "radix_passes",
                 "grid_x", "grid_y", "grid_z", "max_points_per_cell", "status",
-                "work_cells", "giant_root"] + ["counter%d" % i for i in range(8)]
+                "work_cells", "giant_root"] + ["counter%d" % i for i in range(8)] + [
+                "column_index"]
 
 
 class FecError(RuntimeError):

@@ -265,13 +265,14 @@ int32_t fec_workspace_stats(const void *workspace, void *stream, int64_t *out, i
     if (hipMemcpyAsync(&P, workspace, sizeof P, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return fail(FEC_EDEVICE, "reading the workspace failed");
-    const int64_t v[21] = {P.n,  P.nvalid, P.M,  P.Mcol,     P.key_bits, P.npasses, P.NX,
+    const int64_t v[22] = {P.n,  P.nvalid, P.M,  P.Mcol,     P.key_bits, P.npasses, P.NX,
                            P.NY, P.NZ,     P.max_cell, P.status, P.nwork,   P.giant,
                            (int64_t)P.counters[0], (int64_t)P.counters[1],
                            (int64_t)P.counters[2], (int64_t)P.counters[3],
                            (int64_t)P.counters[4], (int64_t)P.counters[5],
-                           (int64_t)P.counters[6], (int64_t)P.counters[7]};
-    const int32_t c = max_out < 21 ? max_out : 21;
+                           (int64_t)P.counters[6], (int64_t)P.counters[7],
+                           P.dense_cols ? 1 : (P.hashed_cols ? 2 : 0)};
+    const int32_t c = max_out < 22 ? max_out : 22;
     for (int32_t i = 0; i < c; ++i) out[i] = v[i];
     ok();
     return c;

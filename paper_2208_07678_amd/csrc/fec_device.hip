@@ -210,6 +210,65 @@ __device__ __forceinline__ int64_t block_excl_scan_i64(int64_t v, int64_t *s_tmp
     return before + x - v;
 }
 
+// Plans frame f from its reduced bounding box (r = min x, y, z, max x, y,
+// z) and finite-point count: argument checks, origin, cell side, extent.
+// One thread per frame.
+__device__ void plan_frame(int f, const float (&r)[6], uint64_t cnt, Frame *__restrict__ frames,
+                           int nframes, int64_t n, const int64_t *__restrict__ offs,
+                           const float *__restrict__ d_arr, const int32_t *__restrict__ min_arr,
+                           const int32_t *__restrict__ max_arr, float d_one, int32_t min_one,
+                           int32_t max_one, int32_t *s_bad) {
+    Frame F;
+    if (offs) {
+        const int64_t a = offs[f], b = offs[f + 1];
+        if (a > b || (f == 0 && a != 0) || (f == nframes - 1 && b != n)) *s_bad = 1;
+    }
+    frame_range(offs, n, f, F.off0, F.off1);
+    F.d = d_arr ? d_arr[f] : d_one;
+    const int32_t mn = min_arr ? min_arr[f] : min_one;
+    F.max_size = max_arr ? max_arr[f] : max_one;
+    F.min_size = mn < 1 ? 1 : mn;
+    F.d2 = __fmul_rn(F.d, F.d);
+    F.status = kStatusOk;
+    // the same argument checks as the host applies to a single cloud
+    if (!isfinite(F.d) || !(F.d > 0.0f) || !(F.d2 >= FLT_MIN) || isinf(F.d2) ||
+        mn > F.max_size)
+        F.status = kStatusInval;
+    F.kept = 0;
+    F.giant = -1;
+    F.cell0 = 0;
+    F.xoff = 0;
+    int64_t N3[3] = {1, 1, 1};
+    double o3[3] = {0.0, 0.0, 0.0};
+    double inv = 0.0;
+    if (F.status == kStatusOk) {
+        const double side = (double)F.d * (1.0 - 0x1p-10) / sqrt(3.0);
+        inv = 1.0 / side;
+        if (cnt > 0) {
+            for (int a = 0; a < 3; ++a) {
+                o3[a] = (double)r[a];
+                const double ext = ((double)r[a + 3] - (double)r[a]) * inv;
+                if (!(ext < 0x1p31)) {
+                    F.status = kStatusRange;
+                } else {
+                    N3[a] = (int64_t)floor(ext) + 1;
+                }
+            }
+        }
+    }
+    if (F.status != kStatusOk) {  // a refused frame holds no cell
+        inv = 0.0;
+        N3[0] = N3[1] = N3[2] = 1;
+        o3[0] = o3[1] = o3[2] = 0.0;
+        cnt = 0;
+    }
+    F.nvalid = (int64_t)cnt;
+    F.inv_s = inv;
+    F.ox = o3[0]; F.oy = o3[1]; F.oz = o3[2];
+    F.NX = N3[0]; F.NY = N3[1]; F.NZ = N3[2];
+    frames[f] = F;
+}
+
 // Fixes every frame's grid, stacks the frames' grids along x, and fixes the
 // key layout and the number of radix passes.  One block: wave w plans the
 // frames w, w + 4, ...; then the block scans the frames' widths.
@@ -230,6 +289,21 @@ __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ parti
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
 
+    if (per_frame < 16) {
+        // many frames, few partial boxes each: one thread per frame
+        for (int f = threadIdx.x; f < nframes; f += kBlock) {
+            float r[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+            uint64_t cnt = 0;
+            for (int b = 0; b < per_frame; ++b) {
+                const float *q = partials + ((size_t)f * per_frame + b) * 8;
+                for (int a = 0; a < 3; ++a) r[a] = fminf(r[a], q[a]);
+                for (int a = 3; a < 6; ++a) r[a] = fmaxf(r[a], q[a]);
+                cnt += __float_as_uint(q[6]);
+            }
+            plan_frame(f, r, cnt, frames, nframes, n, offs, d_arr, min_arr, max_arr, d_one,
+                       min_one, max_one, &s_bad);
+        }
+    } else
     for (int f = wave; f < nframes; f += kBlock / 64) {
         float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY;
         float hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
@@ -248,56 +322,9 @@ __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ parti
             cnt += __shfl_xor(cnt, o);
         }
         if (lane != 0) continue;
-        Frame F;
-        if (offs) {
-            const int64_t a = offs[f], b = offs[f + 1];
-            if (a > b || (f == 0 && a != 0) || (f == nframes - 1 && b != n)) s_bad = 1;
-        }
-        frame_range(offs, n, f, F.off0, F.off1);
-        F.d = d_arr ? d_arr[f] : d_one;
-        const int32_t mn = min_arr ? min_arr[f] : min_one;
-        F.max_size = max_arr ? max_arr[f] : max_one;
-        F.min_size = mn < 1 ? 1 : mn;
-        F.d2 = __fmul_rn(F.d, F.d);
-        F.status = kStatusOk;
-        // the same argument checks as the host applies to a single cloud
-        if (!isfinite(F.d) || !(F.d > 0.0f) || !(F.d2 >= FLT_MIN) || isinf(F.d2) ||
-            mn > F.max_size)
-            F.status = kStatusInval;
-        F.kept = 0;
-        F.giant = -1;
-        F.cell0 = 0;
-        F.xoff = 0;
-        int64_t N3[3] = {1, 1, 1};
-        double o3[3] = {0.0, 0.0, 0.0};
         const float r[6] = {lo0, lo1, lo2, hi0, hi1, hi2};
-        double inv = 0.0;
-        if (F.status == kStatusOk) {
-            const double side = (double)F.d * (1.0 - 0x1p-10) / sqrt(3.0);
-            inv = 1.0 / side;
-            if (cnt > 0) {
-                for (int a = 0; a < 3; ++a) {
-                    o3[a] = (double)r[a];
-                    const double ext = ((double)r[a + 3] - (double)r[a]) * inv;
-                    if (!(ext < 0x1p31)) {
-                        F.status = kStatusRange;
-                    } else {
-                        N3[a] = (int64_t)floor(ext) + 1;
-                    }
-                }
-            }
-        }
-        if (F.status != kStatusOk) {  // a refused frame holds no cell
-            inv = 0.0;
-            N3[0] = N3[1] = N3[2] = 1;
-            o3[0] = o3[1] = o3[2] = 0.0;
-            cnt = 0;
-        }
-        F.nvalid = (int64_t)cnt;
-        F.inv_s = inv;
-        F.ox = o3[0]; F.oy = o3[1]; F.oz = o3[2];
-        F.NX = N3[0]; F.NY = N3[1]; F.NZ = N3[2];
-        frames[f] = F;
+        plan_frame(f, r, cnt, frames, nframes, n, offs, d_arr, min_arr, max_arr, d_one, min_one,
+                   max_one, &s_bad);
     }
     __syncthreads();
 
@@ -356,6 +383,12 @@ __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ parti
     P->giant = -1;
     P->nwork = 0;
     P->dense_cols = ((double)NX * (double)P->NYp <= (double)colgrid_cap) ? 1 : 0;
+    P->hashed_cols = 0;
+    uint64_t hcap = 1;
+    while (hcap * 2 <= colgrid_cap / 2) hcap *= 2;  // 8-byte slots in 4-byte entries
+    P->hcap = hcap;
+    P->hmask = 0;
+    P->hshift = 64;
     const int B = P->bx + P->by + P->bz;
     const int kb = B + ((nvalid < n) ? 1 : 0);
     int ib = bits_for(n);
@@ -745,6 +778,20 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const uint32_t *__restrict__
             P->M = 0;
             P->Mcol = 0;
         }
+        // no dense index: hash the columns when key and cell fit one slot
+        // and the table stays at most half full
+        if (!P->dense_cols && P->bx + P->by <= 33) {
+            uint64_t slots = 1024;
+            while (slots < 4ull * Mc) slots *= 2;
+            if (slots > P->hcap) slots = P->hcap;
+            if (2ull * Mc <= slots) {
+                int lg = 0;
+                while ((1ull << lg) < slots) ++lg;
+                P->hashed_cols = 1;
+                P->hmask = slots - 1;
+                P->hshift = 64 - lg;
+            }
+        }
     }
 }
 
@@ -771,6 +818,13 @@ __device__ __forceinline__ int frame_of_point(const Frame *frames, int nframes, 
     return lo;
 }
 
+// Column hash slots: column key << 31 | first cell; all ones = empty.
+constexpr uint64_t kHashEmpty = ~0ull;
+
+__device__ __forceinline__ uint64_t col_hash(uint64_t ck, int shift) {
+    return (ck * 0x9E3779B97F4A7C15ull) >> shift;
+}
+
 // ------------------------------------------------------------- 7. cells
 // Cell table (first sorted position and key of every occupied cell) and
 // column table (key and first cell of every occupied column (cx, cy)), plus
@@ -787,12 +841,19 @@ __global__ __launch_bounds__(kBlock) void k_cells(const uint64_t *__restrict__ s
                                                   uint32_t *__restrict__ csize,
                                                   uint32_t *__restrict__ ccanon,
                                                   Frame *__restrict__ frames,
-                                                  uint32_t *__restrict__ cell_frame) {
+                                                  uint32_t *__restrict__ cell_frame,
+                                                  uint64_t *__restrict__ hslots) {
     if (P->status != kStatusOk) return;
     const uint64_t *srt = (P->npasses & 1) ? s1 : s0;
     const int64_t nvalid = P->nvalid;
     const int ks = P->key_shift, bz = P->bz, xshift = P->by + P->bz;
     const int nframes = P->nframes;
+    if (P->hashed_cols) {  // empty every slot of the column hash (filled by k_colgrid)
+        const uint64_t slots = P->hmask + 1;
+        for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < slots;
+             i += (uint64_t)gridDim.x * kBlock)
+            hslots[i] = kHashEmpty;
+    }
     const int64_t base = (int64_t)blockIdx.x * kTile;
     const int wave = threadIdx.x >> 6, lane = __lane_id();
     __shared__ uint32_t s_tot[2][kItems][kBlock / 64];
@@ -895,6 +956,26 @@ __global__ __launch_bounds__(kBlock) void k_colgrid(const uint64_t *__restrict__
         col_cell[Mcol] = (uint32_t)P->M;
         cell_start[P->M] = (uint32_t)P->nvalid;
     }
+    if (P->hashed_cols) {
+        // column keys are distinct, so each insert claims one empty slot; the
+        // table has more slots than columns, so every probe sequence ends
+        uint64_t *hs = reinterpret_cast<uint64_t *>(colgrid);
+        const uint64_t mask = P->hmask;
+        const int shift = P->hshift;
+        for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < Mcol;
+             c += (int64_t)gridDim.x * kBlock) {
+            const uint64_t ck = col_key[c];
+            const uint64_t v = (ck << 31) | (uint64_t)col_cell[c];
+            uint64_t h = col_hash(ck, shift);
+            for (uint64_t probe = 0; probe <= mask; ++probe) {
+                if (atomicCAS((unsigned long long *)(hs + h), (unsigned long long)kHashEmpty,
+                              (unsigned long long)v) == kHashEmpty)
+                    break;
+                h = (h + 1) & mask;
+            }
+        }
+        return;
+    }
     if (!P->dense_cols) return;
     const Grid g = grid_of(P);
     const int lane = __lane_id();
@@ -925,31 +1006,102 @@ __global__ __launch_bounds__(kBlock) void k_colgrid(const uint64_t *__restrict__
     }
 }
 
-// First cell of column (cx, cy), or false when the column is empty or off
-// the grid.
-__device__ __forceinline__ bool find_column(const Grid &g, int64_t cx, int64_t cy, int dense,
-                                            const uint32_t *__restrict__ colgrid,
-                                            const uint32_t *__restrict__ colbits,
-                                            const uint64_t *__restrict__ col_key,
-                                            const uint32_t *__restrict__ col_cell, int64_t Mcol,
-                                            uint32_t &first) {
-    if (cx < 0 || cx >= g.NX || cy < 0 || cy >= g.NY) return false;
-    if (dense) {
-        const uint64_t idx = (uint64_t)(cx * g.NYp + cy);
-        if (!((colbits[idx >> 5] >> (idx & 31)) & 1u)) return false;
-        first = colgrid[idx];
-        return true;
+// Column index in use: dense table, hash table, or binary search over the
+// sorted column keys.
+struct ColIndex {
+    int mode;  // kColDense, kColHash, kColSearch
+    const uint32_t *colgrid, *colbits;
+    const uint64_t *hs;
+    uint64_t hmask;
+    int hshift;
+    const uint64_t *col_key;
+    const uint32_t *col_cell;
+    int64_t Mcol;
+};
+constexpr int kColSearch = 0, kColDense = 1, kColHash = 2;
+
+__device__ __forceinline__ ColIndex colindex_of(const Params *P, const uint32_t *colgrid,
+                                                const uint32_t *colbits,
+                                                const uint64_t *col_key,
+                                                const uint32_t *col_cell) {
+    ColIndex c;
+    c.mode = P->dense_cols ? kColDense : (P->hashed_cols ? kColHash : kColSearch);
+    c.colgrid = colgrid;
+    c.colbits = colbits;
+    c.hs = reinterpret_cast<const uint64_t *>(colgrid);
+    c.hmask = P->hmask;
+    c.hshift = P->hshift;
+    c.col_key = col_key;
+    c.col_cell = col_cell;
+    c.Mcol = P->Mcol;
+    return c;
+}
+
+// Continues a hash probe sequence from slot h holding v until the column's
+// slot or an empty one.
+__device__ __forceinline__ bool hash_resolve(const ColIndex &ci, uint64_t want, uint64_t h,
+                                             uint64_t v, uint32_t &first) {
+    for (uint64_t probe = 0; probe <= ci.hmask; ++probe) {
+        if (v == kHashEmpty) return false;
+        if ((v >> 31) == want) {
+            first = (uint32_t)(v & 0x7FFFFFFFu);
+            return true;
+        }
+        h = (h + 1) & ci.hmask;
+        v = ci.hs[h];
     }
-    const uint64_t want = g.col_key((uint64_t)cx, (uint64_t)cy);
-    int64_t lo = 0, hi = Mcol;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (col_key[mid] < want) lo = mid + 1;
-        else hi = mid;
+    return false;
+}
+
+// Several column lookups with their first memory access issued together:
+// has[o] / first[o] for columns (nx[o], ny[o]), o < K.
+template <int K>
+__device__ __forceinline__ void find_columns(const Grid &g, const ColIndex &ci,
+                                             const int64_t (&nx)[K], const int64_t (&ny)[K],
+                                             bool (&has)[K], uint32_t (&first)[K]) {
+    bool in[K];
+#pragma unroll
+    for (int o = 0; o < K; ++o) in[o] = nx[o] >= 0 && nx[o] < g.NX && ny[o] >= 0 && ny[o] < g.NY;
+    if (ci.mode == kColDense) {
+#pragma unroll
+        for (int o = 0; o < K; ++o) {
+            const uint64_t idx = in[o] ? (uint64_t)(nx[o] * g.NYp + ny[o]) : 0;
+            const uint32_t wd = in[o] ? ci.colbits[idx >> 5] : 0u;
+            first[o] = in[o] ? ci.colgrid[idx] : 0u;
+            has[o] = (wd >> (idx & 31)) & 1u;
+        }
+    } else if (ci.mode == kColHash) {
+        uint64_t h[K], v[K], want[K];
+#pragma unroll
+        for (int o = 0; o < K; ++o) {
+            want[o] = g.col_key((uint64_t)nx[o], (uint64_t)ny[o]);
+            h[o] = col_hash(want[o], ci.hshift);
+            v[o] = in[o] ? ci.hs[h[o]] : kHashEmpty;
+        }
+#pragma unroll
+        for (int o = 0; o < K; ++o) {
+            first[o] = 0;
+            has[o] = in[o] && hash_resolve(ci, want[o], h[o], v[o], first[o]);
+        }
+    } else {
+#pragma unroll
+        for (int o = 0; o < K; ++o) {
+            has[o] = false;
+            first[o] = 0;
+            if (!in[o]) continue;
+            const uint64_t want = g.col_key((uint64_t)nx[o], (uint64_t)ny[o]);
+            int64_t lo = 0, hi = ci.Mcol;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (ci.col_key[mid] < want) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < ci.Mcol && ci.col_key[lo] == want) {
+                has[o] = true;
+                first[o] = ci.col_cell[lo];
+            }
+        }
     }
-    if (lo >= Mcol || col_key[lo] != want) return false;
-    first = col_cell[lo];
-    return true;
 }
 
 // ------------------------------------------------------------- 8. hooking
@@ -1020,12 +1172,34 @@ __device__ __forceinline__ int32_t uf_link_roots(int32_t *par, int32_t a, int32_
 
 // Is there a joined pair between the points [sA, eA) and [sB, eB)?  Stops at
 // the first one.
-__device__ __forceinline__ bool any_joined(const float4 *__restrict__ spts, uint32_t sA,
-                                           uint32_t eA, uint32_t sB, uint32_t eB, float d2) {
+// Point by point: for pairs of small cells that are usually joined at the
+// first pair.
+__device__ __forceinline__ bool any_joined_1(const float4 *__restrict__ spts, uint32_t sA,
+                                             uint32_t eA, uint32_t sB, uint32_t eB, float d2) {
     for (uint32_t a = sA; a < eA; ++a) {
         const float4 pa = spts[a];
         for (uint32_t b = sB; b < eB; ++b)
             if (joined(pa.x, pa.y, pa.z, spts[b], d2)) return true;
+    }
+    return false;
+}
+
+// The points of B are read four at a time (independent loads in flight
+// together); an index past the end re-reads B's last point, which changes
+// nothing.
+__device__ __forceinline__ bool any_joined(const float4 *__restrict__ spts, uint32_t sA,
+                                           uint32_t eA, uint32_t sB, uint32_t eB, float d2) {
+    for (uint32_t a = sA; a < eA; ++a) {
+        const float4 pa = spts[a];
+        for (uint32_t b = sB; b < eB; b += 4) {
+            float4 q[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) q[j] = spts[b + j < eB ? b + j : eB - 1];
+            bool hit = false;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) hit |= joined(pa.x, pa.y, pa.z, q[j], d2);
+            if (hit) return true;
+        }
     }
     return false;
 }
@@ -1072,8 +1246,8 @@ __global__ __launch_bounds__(kBlock) void k_runs1(const float4 *__restrict__ spt
             const uint64_t kp = cell_key[A - 1], ka = cell_key[A];
             if (next_is_near(g, kp, ka)) {  // same x, so the same frame
                 const float d2 = batched ? frames[cell_frame[A]].d2 : d2_one;
-                head = !any_joined(spts, cell_start[A - 1], cell_start[A], cell_start[A],
-                                   cell_start[A + 1], d2);
+                head = !any_joined_1(spts, cell_start[A - 1], cell_start[A], cell_start[A],
+                                     cell_start[A + 1], d2);
             }
         }
         heads[A] = head ? 1 : 0;
@@ -1144,6 +1318,28 @@ __global__ __launch_bounds__(kBlock) void k_runs2(const uint8_t *__restrict__ he
     }
 }
 
+// Position of the first cell of column `want` with z >= zt, or of the cell
+// after the column when it has none, given the column's first cell fc (its z
+// is z0 < zt) and a position lo <= the answer.  The cells of a column have
+// distinct, increasing z, so the answer is at most fc + (zt - z0); a column
+// without gaps has it exactly there, which is tried first.  Otherwise a
+// binary search over the sorted cell keys.
+__device__ __forceinline__ uint32_t column_seek(const uint64_t *__restrict__ cell_key, int64_t M,
+                                                int bz, uint64_t want, uint32_t fc, int64_t z0,
+                                                uint32_t lo, int64_t zt) {
+    int64_t hi = (int64_t)fc + (zt - z0);
+    if (hi > M) hi = M;
+    const uint64_t T = (want << bz) | (uint64_t)zt;
+    if (hi < M && cell_key[hi] == T) return (uint32_t)hi;
+    int64_t a = lo, b = hi;
+    while (a < b) {
+        const int64_t mid = (a + b) >> 1;
+        if (cell_key[mid] < T) a = mid + 1;
+        else b = mid;
+    }
+    return (uint32_t)a;
+}
+
 // Forward half of the 5x5x5 stencil by column offset (dx, dy): the near
 // shell (max(|dx|,|dy|,|dz|) == 1) uses the first four columns with
 // |dz| <= 1; the own column contributes dz = +1.
@@ -1161,8 +1357,9 @@ __constant__ StencilCol kNearCols[4] = {{0, 1}, {1, -1}, {1, 0}, {1, 1}};
 // cell's own key, points and parent; (2) occupancy bit and index entry of
 // the four neighbour columns; (3) the first kNearK cells of each of those
 // columns; (4) the parents of every candidate cell.  Only then are the
-// candidates whose component differs tested one by one.  Columns with more
-// than kNearK cells in reach fall back to a plain scan.
+// candidates whose component differs tested one by one.  When the cells
+// loaded from a column stop below A's reach (a tall column), the column's
+// cells within reach are located directly (column_seek) and tested after.
 constexpr int kNearK = 3;
 
 __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__ spts,
@@ -1176,8 +1373,8 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
                                                       const uint32_t *__restrict__ cell_frame,
                                                       int32_t *cpar, const Params *__restrict__ P) {
     if (P->status != kStatusOk) return;
-    const int64_t M = P->M, Mcol = P->Mcol;
-    const int dense = P->dense_cols;
+    const int64_t M = P->M;
+    const ColIndex ci = colindex_of(P, colgrid, colbits, col_key, col_cell);
     const float d2_one = P->d2;
     const bool batched = P->nframes > 1;
     const Grid g = grid_of(P);
@@ -1201,23 +1398,15 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
         bool has[kC];
         uint32_t fc[kC];
         uint64_t want[kC];
+        int64_t nxs[kC], nys[kC];
 #pragma unroll
         for (int o = 0; o < kC; ++o) {
             const StencilCol sc = kNearCols[o];
-            const int64_t nx = cx + sc.dx, ny = cy + sc.dy;
-            want[o] = g.col_key((uint64_t)nx, (uint64_t)ny);
-            if (dense) {
-                const bool in = nx < g.NX && ny >= 0 && ny < g.NY;
-                const uint64_t idx = in ? (uint64_t)(nx * g.NYp + ny) : 0;
-                const uint32_t wd = in ? colbits[idx >> 5] : 0u;
-                const uint32_t f = in ? colgrid[idx] : 0u;
-                has[o] = (wd >> (idx & 31)) & 1u;
-                fc[o] = f;
-            } else {
-                has[o] = find_column(g, nx, ny, 0, colgrid, colbits, col_key, col_cell, Mcol,
-                                     fc[o]);
-            }
+            nxs[o] = cx + sc.dx;
+            nys[o] = cy + sc.dy;
+            want[o] = g.col_key((uint64_t)nxs[o], (uint64_t)nys[o]);
         }
+        find_columns<kC>(g, ci, nxs, nys, has, fc);
         // round 3: first cells of each column
         uint64_t kk[kC][kNearK];
 #pragma unroll
@@ -1281,14 +1470,25 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
             }
         }
         FEC_COUNT(P, 4, __popc(ovf));
-        // columns with more cells in reach than were loaded
+        // columns with cells in reach beyond the loaded ones: at most three
+        // more (z within cz +- 1, distinct), from the first one not below
         if (ovf) {
             for (int o = 0; o < kC; ++o) {
                 if (!((ovf >> o) & 1u)) continue;
-                for (uint32_t B = fc[o] + kNearK; (int64_t)B < M; ++B) {
-                    const uint64_t kb = cell_key[B];
-                    if ((kb >> g.bz) != want[o]) break;
-                    const int64_t dz = (int64_t)(kb & g.zmask) - cz;
+                const int64_t zl = (int64_t)(kk[o][kNearK - 1] & g.zmask);
+                const uint32_t st =
+                    zl >= cz - 1 ? fc[o] + kNearK
+                                 : column_seek(cell_key, M, g.bz, want[o], fc[o],
+                                               (int64_t)(kk[o][0] & g.zmask), fc[o] + kNearK,
+                                               cz - 1);
+                uint64_t kx[3];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) kx[j] = (int64_t)st + j < M ? cell_key[st + j] : ~0ull;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const uint32_t B = st + j;
+                    if ((int64_t)B >= M || (kx[j] >> g.bz) != want[o]) break;
+                    const int64_t dz = (int64_t)(kx[j] & g.zmask) - cz;
                     if (dz > 1) break;
                     if (dz < -1) continue;
                     const int32_t r = uf_find(cpar, (int32_t)B);
@@ -1476,9 +1676,9 @@ __global__ __launch_bounds__(kBlock) void k_hook_far(const float4 *__restrict__ 
                                                       const uint32_t *__restrict__ cell_frame,
                                                       int32_t *cpar, const Params *__restrict__ P) {
     if (P->status != kStatusOk) return;
-    const int64_t M = P->M, Mcol = P->Mcol;
+    const int64_t M = P->M;
     const uint32_t nwork = P->nwork;
-    const int dense = P->dense_cols;
+    const ColIndex ci = colindex_of(P, colgrid, colbits, col_key, col_cell);
     const float d2_one = P->d2;
     const bool batched = P->nframes > 1;
     const Grid g = grid_of(P);
@@ -1524,25 +1724,18 @@ __global__ __launch_bounds__(kBlock) void k_hook_far(const float4 *__restrict__ 
             bool has[kG];
             uint32_t fc[kG];
             uint64_t want[kG];
+            int64_t nxs[kG], nys[kG];
 #pragma unroll
             for (int o = 0; o < kG; ++o) {
                 int q = g0 + o;
                 q = q >= 12 ? q + 1 : q;  // skip (0, 0)
                 dxs[o] = q / 5 - 2;
                 dys[o] = q % 5 - 2;
-                const int64_t nx = cx + dxs[o], ny = cy + dys[o];
-                want[o] = g.col_key((uint64_t)nx, (uint64_t)ny);
-                if (dense) {
-                    const bool in = nx >= 0 && nx < g.NX && ny >= 0 && ny < g.NY;
-                    const uint64_t idx = in ? (uint64_t)(nx * g.NYp + ny) : 0;
-                    const uint32_t wd = in ? colbits[idx >> 5] : 0u;
-                    fc[o] = in ? colgrid[idx] : 0u;
-                    has[o] = (wd >> (idx & 31)) & 1u;
-                } else {
-                    has[o] = find_column(g, nx, ny, 0, colgrid, colbits, col_key, col_cell, Mcol,
-                                         fc[o]);
-                }
+                nxs[o] = cx + dxs[o];
+                nys[o] = cy + dys[o];
+                want[o] = g.col_key((uint64_t)nxs[o], (uint64_t)nys[o]);
             }
+            find_columns<kG>(g, ci, nxs, nys, has, fc);
             uint64_t kk[kG][kK];
 #pragma unroll
             for (int o = 0; o < kG; ++o)
@@ -1576,16 +1769,29 @@ __global__ __launch_bounds__(kBlock) void k_hook_far(const float4 *__restrict__ 
 #pragma unroll
             for (int i = 0; i < kG * kK; ++i)
                 if ((cm >> i) & 1u) pair(fc[i / kK] + (uint32_t)(i % kK), rb[i]);
+            // columns with cells in reach beyond the loaded ones (z within
+            // cz +- 2, distinct): located directly, at most five
             if (ovf) {
                 for (int o = 0; o < kG; ++o) {
                     if (!((ovf >> o) & 1u)) continue;
                     const bool near_col =
                         dxs[o] >= -1 && dxs[o] <= 1 && dys[o] >= -1 && dys[o] <= 1;
                     const bool fwd = dxs[o] > 0 || (dxs[o] == 0 && dys[o] > 0);
-                    for (uint32_t B = fc[o] + kK; (int64_t)B < M; ++B) {
-                        const uint64_t kb = cell_key[B];
-                        if ((kb >> g.bz) != want[o]) break;
-                        const int64_t dz = (int64_t)(kb & g.zmask) - cz;
+                    const int64_t zl = (int64_t)(kk[o][kK - 1] & g.zmask);
+                    const uint32_t st =
+                        zl >= cz - 2 ? fc[o] + kK
+                                     : column_seek(cell_key, M, g.bz, want[o], fc[o],
+                                                   (int64_t)(kk[o][0] & g.zmask), fc[o] + kK,
+                                                   cz - 2);
+                    uint64_t kx[5];
+#pragma unroll
+                    for (int j = 0; j < 5; ++j)
+                        kx[j] = (int64_t)st + j < M ? cell_key[st + j] : ~0ull;
+#pragma unroll
+                    for (int j = 0; j < 5; ++j) {
+                        const uint32_t B = st + j;
+                        if ((int64_t)B >= M || (kx[j] >> g.bz) != want[o]) break;
+                        const int64_t dz = (int64_t)(kx[j] & g.zmask) - cz;
                         if (dz > 2) break;
                         if (dz < -2 || (near_col && dz >= -1 && dz <= 1)) continue;
                         if (fwd || is_giant(gbits, B)) pair(B, cpar[B]);
@@ -1652,9 +1858,12 @@ __global__ __launch_bounds__(kBlock) void k_final_cells(const int32_t *__restric
             r = cpar[A];
             const uint32_t s = cell_start[A], e = cell_start[A + 1];
             cnt = e - s;
-            for (uint32_t p = s; p < e; ++p) {
-                const uint32_t o = sorig[p];
-                mn = o < mn ? o : mn;
+            for (uint32_t p = s; p < e; p += 4) {  // four loads in flight
+                uint32_t o[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) o[j] = sorig[p + j < e ? p + j : e - 1];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) mn = o[j] < mn ? o[j] : mn;
             }
             cmax = cnt > cmax ? cnt : cmax;
         }
@@ -1733,7 +1942,14 @@ __global__ __launch_bounds__(kBlock) void k_final_labels(const int32_t *__restri
             }
         }
         const uint32_t s = cell_start[A], e = cell_start[A + 1];
-        for (uint32_t p = s; p < e; ++p) labels[sorig[p]] = lab;
+        for (uint32_t p = s; p < e; p += 4) {  // four loads in flight
+            uint32_t o[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) o[j] = sorig[p + j < e ? p + j : e - 1];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (p + j < e) labels[o[j]] = lab;
+        }
     }
     // points sorted after every cell (non-finite, or of a refused frame):
     // singletons
@@ -1840,9 +2056,15 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     int64_t nb_pts = (n + kBlock - 1) / kBlock;
     const int nb_stream = (int)(nb_pts > 8192 ? 8192 : (nb_pts < 1 ? 1 : nb_pts));
     const int nb_cells = (int)(nb_pts > kCellBlocks ? kCellBlocks : (nb_pts < 1 ? 1 : nb_pts));
-    // key blocks per frame: about nb_stream in all, at least one per frame
-    int keys_pf = nb_stream / nframes;
-    keys_pf = keys_pf < 1 ? 1 : keys_pf;
+    // key blocks per frame: one cloud takes the streaming grid; frames take
+    // about one block per 2048 points of an average frame (each block flushes
+    // a full digit histogram, so tiny blocks would cost more in flushes)
+    int keys_pf = nb_stream;
+    if (nframes > 1) {
+        const int64_t per = (n / nframes + 2047) / 2048;
+        keys_pf = (int)(per < nb_stream / nframes ? per : nb_stream / nframes);
+        keys_pf = keys_pf < 1 ? 1 : keys_pf;
+    }
     const int nb_finish = (nframes + kBlock - 1) / kBlock;
     // Passes beyond the device-side count return at once; the pair-mode
     // fallback can need up to a full 64-bit key.
@@ -1882,7 +2104,8 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     FEC_LAUNCH(kStTileScan, k_tile_scan<<<1, 1024, 0, st>>>(tile_cnt, tile_off, ntiles, P));
     FEC_LAUNCH(kStCells, k_cells<<<(unsigned)ntiles, kBlock, 0, st>>>(
                              keys0, keys1, P, tile_off, cell_start, cell_key, col_key, col_cell,
-                             cpar, csize, ccanon, frames, cell_frame));
+                             cpar, csize, ccanon, frames, cell_frame,
+                             reinterpret_cast<uint64_t *>(colgrid)));
     FEC_LAUNCH(kStColGrid, k_colgrid<<<nb_cells, kBlock, 0, st>>>(col_key, col_cell, cell_start,
                                                                    colgrid, colbits, P));
     // runs, near shell, giant component, far shell

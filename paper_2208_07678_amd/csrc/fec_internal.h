@@ -82,6 +82,13 @@ struct Params {
     uint32_t pad1;
     int32_t kept;         // kept clusters
     int32_t max_cell;     // largest number of points in one cell
+    // Hashed column index (when the dense one does not fit): open addressing
+    // with linear probing over 64-bit slots (column key << 31 | first cell,
+    // all ones = empty) in the dense index's memory.
+    int32_t hashed_cols;  // 1: column lookups through the hash table
+    int32_t hshift;       // slot of key k: (k * golden) >> hshift
+    uint64_t hmask;       // slots - 1
+    uint64_t hcap;        // slots that fit in the dense index's memory (a power of two)
     unsigned long long counters[8];  // diagnostic event counts (counting builds only)
     uint32_t hist[kMaxPasses][kRadix];
 };

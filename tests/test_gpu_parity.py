@@ -183,3 +183,29 @@ def test_invariants_map_prefix():
     filt, kf = gpu_cluster(xyz, 0.2, 100, 5000000)
     assert invariants.filter_problems(filt, got, 100, 5000000) == []
     assert invariants.count_kept(filt) == kf
+
+
+def test_column_index_modes():
+    # each way of finding a neighbour column, checked against the oracle:
+    # dense table (compact plane), hash table (sparse plane), binary search
+    # (column key too wide for a hash slot)
+    import torch
+
+    import paper_2208_07678_amd as fec
+    rng = np.random.default_rng(21)
+    sparse = (rng.uniform(0, 400, size=(300, 3)) * np.array([1, 1, 0.01])).astype(np.float32)
+    sparse = np.repeat(sparse, 20, axis=0) + rng.normal(0, 0.15, (6000, 3)).astype(np.float32)
+    centres = rng.uniform(0, 100, size=(400, 3))
+    wide = (np.repeat(centres, 8, axis=0) + rng.uniform(-3e-4, 3e-4, (3200, 3))).astype(np.float32)
+    cases = [("compact", synth.random_cloud(20000, extent=(10, 10, 2), seed=5), 0.3, 1),
+             ("sparse", sparse.astype(np.float32), 0.35, 2),
+             ("wide", wide, 1e-3, 0)]
+    for tag, x, d, mode in cases:
+        say("column index", tag)
+        ws = fec.new_workspace(x.shape[0], "cuda:0")
+        got, k = gpu_cluster(x, d, 1, x.shape[0], workspace=ws)
+        assert fec.workspace_stats(ws)["column_index"] == mode, tag
+        want, wk = oracle.fec(x, d, 1, x.shape[0])
+        assert np.array_equal(got, want), "%s: %s" % (tag, describe_mismatch(got, want))
+        assert k == wk
+    torch.cuda.synchronize()
