@@ -214,13 +214,143 @@ def bench_batch(args) -> None:
     print(json.dumps(out), flush=True)
 
 
+def bench_serve(args) -> None:
+    """The serving engine on a Poisson request stream, beside plain
+    per-request FIFO calls on the same trace (one JSON line): latency
+    percentiles at the stream's rate, and frames/s with every request
+    available at once (saturated)."""
+    import numpy as np
+    import torch
+
+    import paper_2208_07678_amd as fec
+    import synth
+
+    t_gen = time.perf_counter()
+    frames, arrivals, frame_of, d_of = synth.serve_trace(n_requests=args.requests,
+                                                         rate=args.rate, pool=args.pool)
+    t_gen = time.perf_counter() - t_gen
+    dev = torch.device("cuda:0")
+    pool = [torch.from_numpy(f).to(dev) for f in frames]
+    nreq = len(arrivals)
+    sizes = np.array([pool[int(f)].shape[0] for f in frame_of])
+    max_n = max(int(t.shape[0]) for t in pool)
+    mn, mx = 20, 2**31 - 1
+    ring_n = 1024   # label buffers in flight at most
+    ring = torch.empty((ring_n, max_n), dtype=torch.int32, device=dev)
+    print("bench: serve trace %d requests, pool %d frames (mean %.0f points), generated in "
+          "%.1f s" % (nreq, len(pool), sizes.mean(), t_gen), file=sys.stderr, flush=True)
+
+    def run_engine(times):
+        srv = fec.Server(args.serve_budget_gb << 30, nslots=args.slots,
+                         slot_frames=args.slot_frames)
+        lat = np.zeros(nreq)
+        ks = np.zeros(nreq, dtype=np.int64)
+        i = done = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while done < nreq:
+            now = time.perf_counter() - t0
+            moved = 0
+            while i < nreq and times[i] <= now and i - done < ring_n:
+                t = pool[int(frame_of[i])]
+                srv.submit(t, float(d_of[i]), mn, mx, labels=ring[i % ring_n, :t.shape[0]])
+                i += 1
+                moved += 1
+            moved += srv.pump()
+            for tk, _, k, _ in srv.poll():
+                lat[tk] = time.perf_counter() - t0 - times[tk]
+                ks[tk] = k
+                done += 1
+                moved += 1
+            if not moved:
+                if i >= nreq or i - done >= ring_n:
+                    srv.pump(wait=True)
+                else:
+                    time.sleep(2e-5)
+        elapsed = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return lat, ks, elapsed, st
+
+    def run_plain(times):
+        ws = fec.new_workspace(max_n, dev)
+        kall = torch.empty(nreq, dtype=torch.int32, device=dev)
+        stream = torch.cuda.current_stream(dev)
+        lat = np.zeros(nreq)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(nreq):
+            while time.perf_counter() - t0 < times[i]:
+                pass
+            t = pool[int(frame_of[i])]
+            fec.cluster_async(t, float(d_of[i]), mn, mx, labels=ring[i % ring_n, :t.shape[0]],
+                              k_out=kall[i:i + 1], workspace=ws, stream=stream)
+            stream.synchronize()
+            lat[i] = time.perf_counter() - t0 - times[i]
+        elapsed = time.perf_counter() - t0
+        return lat, kall.cpu().numpy().astype(np.int64), elapsed
+
+    def pct(v, q):
+        return float(np.percentile(v, q) * 1e3)
+
+    zero = np.zeros(nreq)
+    run_engine(zero)  # warm-up
+    s_lat, s_ks, s_el, s_st = run_engine(zero)
+    p_lat0, p_ks0, p_el0 = run_plain(zero)
+    if not np.array_equal(s_ks, p_ks0):
+        raise SystemExit("bench: served and plain kept counts differ")
+    e_lat, e_ks, e_el, e_st = run_engine(arrivals)
+    p_lat, p_ks, p_el = run_plain(arrivals)
+    if not (np.array_equal(e_ks, p_ks) and np.array_equal(e_ks, s_ks)):
+        raise SystemExit("bench: served and plain kept counts differ")
+    out = {
+        "metric": "frames/s served (continuous batching, saturated) with p50/p99 latency at "
+                  "%g requests/s" % args.rate,
+        "value": nreq / s_el,
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": nreq,
+        "warmup": 1,
+        "ms_per_step": s_el * 1e3 / nreq,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "serve", "requests": nreq, "rate_per_s": args.rate,
+                   "pool_frames": len(pool), "mean_points": float(sizes.mean()),
+                   "d_values": sorted(set(float(v) for v in d_of)), "min_size": mn,
+                   "max_size": mx, "slots": args.slots, "slot_frames": args.slot_frames,
+                   "slot_points": s_st["slot_points"]},
+        "saturated": {"served_frames_per_s": nreq / s_el, "plain_frames_per_s": nreq / p_el0,
+                      "speedup": p_el0 / s_el, "batches": s_st["batches"],
+                      "max_batch_frames": s_st["max_batch_frames"],
+                      "max_in_flight": s_st["max_in_flight"]},
+        "poisson": {"served": {"frames_per_s": nreq / e_el, "p50_ms": pct(e_lat, 50),
+                               "p99_ms": pct(e_lat, 99), "batches": e_st["batches"],
+                               "max_batch_frames": e_st["max_batch_frames"],
+                               "max_in_flight": e_st["max_in_flight"]},
+                    "plain_fifo": {"frames_per_s": nreq / p_el, "p50_ms": pct(p_lat, 50),
+                                   "p99_ms": pct(p_lat, 99)}},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="map27m",
-                    choices=["map27m", "lidar120k", "blobs20k", "batch64"])
+                    choices=["map27m", "lidar120k", "blobs20k", "batch64", "serve"])
+    ap.add_argument("--requests", type=int, default=10000, help="serve: requests in the trace")
+    ap.add_argument("--rate", type=float, default=400.0, help="serve: Poisson arrivals per s")
+    ap.add_argument("--pool", type=int, default=512, help="serve: distinct frames in the pool")
+    ap.add_argument("--slots", type=int, default=2, help="serve: batch slots")
+    ap.add_argument("--slot-frames", type=int, default=64, help="serve: requests per batch")
+    ap.add_argument("--serve-budget-gb", type=int, default=16, help="serve: HBM budget")
     ap.add_argument("--cpu-frames", type=int, default=30,
                     help="map frames in the CPU-baseline sample (0 = skip)")
     ap.add_argument("--stages", action="store_true", help="also print a per-stage breakdown")
@@ -239,6 +369,9 @@ def main():
 
     if args.workload == "batch64":
         bench_batch(args)
+        return
+    if args.workload == "serve":
+        bench_serve(args)
         return
 
     import numpy as np  # noqa: F401

@@ -134,6 +134,76 @@ int32_t fec_cluster_batch_async(const float *xyz, int64_t n_total, int32_t nfram
 /* Workspace bytes of fec_cluster_batch_async (0 for invalid sizes). */
 size_t fec_batch_workspace_bytes(int64_t n_total, int32_t nframes);
 
+/*
+ * Serving engine: continuous batching of independent requests (one cloud
+ * each, with its own d and size bounds; the same computation as
+ * fec_cluster_async on that cloud alone, so each request's labels and count
+ * equal its single-call result whatever it was batched with).
+ *
+ * The engine owns nslots batch slots on the current device, each with its
+ * own stream, batched-form workspace and buffers.  Admission is by HBM
+ * footprint: a slot holds at most fec_server_slot_points() points (the most
+ * whose slot footprint, fec_server_slot_bytes(), fits hbm_budget / nslots)
+ * in at most slot_frames requests.  Requests queue in submission order;
+ * fec_server_pump() retires finished batches and launches the head of the
+ * queue into every free slot at once (no waiting for a batch to fill), so
+ * batches overlap on the device.  One host thread drives a server.
+ */
+typedef struct fec_server fec_server;
+
+/* HBM bytes of one slot for slot_points points in slot_frames requests (0 if invalid). */
+size_t fec_server_slot_bytes(int64_t slot_points, int32_t slot_frames);
+
+/*
+ * Creates a server: nslots in [1, 64], slot_frames in [1, 1024].  Returns
+ * FEC_OK and *out, FEC_EINVAL for bad arguments, FEC_ENOMEM when the budget
+ * holds no point per slot or an allocation fails.
+ */
+int32_t fec_server_create(size_t hbm_budget, int32_t nslots, int32_t slot_frames,
+                          fec_server **out);
+
+/* Points one slot admits. */
+int64_t fec_server_slot_points(const fec_server *server);
+
+/*
+ * Queues one request.  xyz (float32 [n][3]) and labels_out (int32 [n]) are
+ * DEVICE pointers (pinned host memory also works, over PCIe) that must stay
+ * valid, and unused by other work, until the request completes; labels_out
+ * then holds the request's labels (as fec_cluster gives them).  Returns
+ * FEC_OK and *ticket (0, 1, 2, ... in submission order); FEC_EINVAL for the
+ * argument checks of fec_cluster; FEC_ENOMEM when n exceeds a slot.
+ */
+int32_t fec_server_submit(fec_server *server, const float *xyz, int64_t n, float d,
+                          int32_t min_size, int32_t max_size, int32_t *labels_out,
+                          int64_t *ticket);
+
+/*
+ * Retires finished batches, then launches queued requests into free slots.
+ * With wait != 0 and nothing retired or launched, blocks until the oldest
+ * batch in flight finishes (returns at once when none is).  Returns the
+ * number of requests completed by this call, or a negative status.
+ */
+int32_t fec_server_pump(fec_server *server, int32_t wait);
+
+/*
+ * Takes up to max completed requests, oldest first: ticket, k (kept
+ * clusters, or a negative FEC_* status) and latency in milliseconds from
+ * submission to retirement by fec_server_pump.  Returns the number taken.
+ */
+int32_t fec_server_poll(fec_server *server, int64_t *tickets, int32_t *k, double *latency_ms,
+                        int32_t max);
+
+/*
+ * out[0] requests submitted, out[1] completed, out[2] batches launched,
+ * out[3] queued now, out[4] slots busy now, out[5] most requests in one
+ * batch, out[6] most batches in flight at once, out[7] points per slot,
+ * out[8] bytes per slot.  Returns the number of values written (<= 9).
+ */
+int32_t fec_server_stats(const fec_server *server, int64_t *out, int32_t max_out);
+
+/* Waits for the server's work and frees it. */
+void fec_server_destroy(fec_server *server);
+
 /* Stream used by fec_cluster (a hipStream_t; NULL = null stream).  Returns FEC_OK. */
 int32_t fec_set_stream(void *stream);
 

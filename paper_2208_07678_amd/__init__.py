@@ -22,7 +22,7 @@ import os
 
 __all__ = [
     "cluster", "cluster_async", "workspace_bytes", "workspace_stats", "FecError",
-    "cluster_batch", "cluster_batch_async", "batch_workspace_bytes", "pack_frames",
+    "cluster_batch", "cluster_batch_async", "batch_workspace_bytes", "pack_frames", "Server",
     "profile_enable", "profile_read", "profile_reset", "stage_names", "lib_path",
     "FEC_OK", "FEC_EINVAL", "FEC_ERANGE", "FEC_ENOMEM", "FEC_EDEVICE",
 ]
@@ -62,6 +62,14 @@ def _load():
         "fec_cluster_batch_async": ([vp, i64, i32, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t,
                                      vp], i32),
         "fec_batch_workspace_bytes": ([i64, i32], ctypes.c_size_t),
+        "fec_server_slot_bytes": ([i64, i32], ctypes.c_size_t),
+        "fec_server_create": ([ctypes.c_size_t, i32, i32, vp], i32),
+        "fec_server_slot_points": ([vp], i64),
+        "fec_server_submit": ([vp, vp, i64, f32, i32, i32, vp, vp], i32),
+        "fec_server_pump": ([vp, i32], i32),
+        "fec_server_poll": ([vp, vp, vp, vp, i32], i32),
+        "fec_server_stats": ([vp, vp, i32], i32),
+        "fec_server_destroy": ([vp], None),
         "fec_set_stream": ([vp], i32),
         "fec_release": ([], None),
         "fec_last_error": ([], ctypes.c_char_p),
@@ -83,7 +91,9 @@ def _load():
 
 EXPORTED = [
     "fec_cluster", "fec_workspace_bytes", "fec_cluster_async", "fec_set_stream", "fec_release",
-    "fec_cluster_batch_async", "fec_batch_workspace_bytes",
+    "fec_cluster_batch_async", "fec_batch_workspace_bytes", "fec_server_slot_bytes",
+    "fec_server_create", "fec_server_slot_points", "fec_server_submit", "fec_server_pump",
+    "fec_server_poll", "fec_server_stats", "fec_server_destroy",
     "fec_last_error", "fec_version", "fec_workspace_stats", "fec_profile_enable",
     "fec_profile_read", "fec_profile_reset", "fec_stage_count", "fec_stage_name",
 ]
@@ -287,6 +297,96 @@ def cluster_batch(xyz, offsets, d, min_size=1, max_size=2**31 - 1, *, workspace=
     labels, k_out, _ = cluster_batch_async(xyz, offsets, d, min_size, max_size, labels=labels,
                                            workspace=workspace, stream=stream)
     return labels, [int(v) for v in k_out.cpu().tolist()]
+
+
+SERVER_STATS_FIELDS = ["submitted", "completed", "batches", "queued", "slots_busy",
+                       "max_batch_frames", "max_in_flight", "slot_points", "slot_bytes"]
+
+
+class Server:
+    """Continuous-batching engine over the C ABI (fec_server_*).
+
+    ``submit`` queues a CUDA float32 [n, 3] cloud (kept referenced until its
+    request completes) and returns its ticket; ``pump`` retires finished
+    batches and launches queued requests into free slots; ``poll`` returns the
+    completed requests as (ticket, labels tensor, k, latency ms).
+    """
+
+    def __init__(self, hbm_budget: int, nslots: int = 2, slot_frames: int = 64):
+        lib = _load()
+        h = ctypes.c_void_p()
+        rc = lib.fec_server_create(int(hbm_budget), int(nslots), int(slot_frames),
+                                   ctypes.byref(h))
+        if rc != FEC_OK:
+            raise FecError(rc, "fec_server_create failed")
+        self._h = h
+        self._live = {}   # ticket -> (xyz, labels) kept alive until done
+
+    @property
+    def slot_points(self) -> int:
+        return int(_load().fec_server_slot_points(self._h))
+
+    def submit(self, xyz, d: float, min_size: int = 1, max_size: int = 2**31 - 1,
+               labels=None) -> int:
+        torch = _torch()
+        _check_xyz(xyz)
+        n = xyz.shape[0]
+        if labels is None:
+            labels = torch.empty(n, dtype=torch.int32, device=xyz.device)
+        t = ctypes.c_int64()
+        rc = _load().fec_server_submit(self._h, ctypes.c_void_p(xyz.data_ptr()), n, float(d),
+                                       int(min_size), int(max_size),
+                                       ctypes.c_void_p(labels.data_ptr()), ctypes.byref(t))
+        if rc != FEC_OK:
+            raise FecError(rc, "submit refused (n=%d, d=%g, min=%d, max=%d)"
+                           % (n, d, min_size, max_size))
+        self._live[t.value] = (xyz, labels)
+        return t.value
+
+    def pump(self, wait: bool = False) -> int:
+        rc = _load().fec_server_pump(self._h, 1 if wait else 0)
+        if rc < 0:
+            raise FecError(rc, "fec_server_pump failed")
+        return rc
+
+    def poll(self, max_items: int = 4096):
+        tk = (ctypes.c_int64 * max_items)()
+        kk = (ctypes.c_int32 * max_items)()
+        lat = (ctypes.c_double * max_items)()
+        c = _load().fec_server_poll(self._h, tk, kk, lat, max_items)
+        out = []
+        for i in range(c):
+            _, labels = self._live.pop(int(tk[i]))
+            out.append((int(tk[i]), labels, int(kk[i]), float(lat[i])))
+        return out
+
+    def stats(self) -> dict:
+        out = (ctypes.c_int64 * len(SERVER_STATS_FIELDS))()
+        c = _load().fec_server_stats(self._h, out, len(SERVER_STATS_FIELDS))
+        return {k: int(out[i]) for i, k in enumerate(SERVER_STATS_FIELDS[:c])}
+
+    def drain(self):
+        """Pumps until every submitted request has completed; returns poll()."""
+        done = []
+        while True:
+            st = self.stats()
+            if st["completed"] >= st["submitted"]:
+                break
+            self.pump(wait=True)
+            done += self.poll()
+        return done + self.poll()
+
+    def close(self):
+        if self._h:
+            _load().fec_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def workspace_stats(workspace, stream=None) -> dict:

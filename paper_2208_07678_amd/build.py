@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfec_hip.so")
-SOURCES = [os.path.join(CSRC, "fec_device.hip"), os.path.join(CSRC, "fec_api.hip")]
+SOURCES = [os.path.join(CSRC, "fec_device.hip"), os.path.join(CSRC, "fec_api.hip"),
+           os.path.join(CSRC, "fec_serve.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

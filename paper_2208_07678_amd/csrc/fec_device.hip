@@ -289,7 +289,40 @@ __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ parti
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
 
-    if (per_frame < 16) {
+    if (nframes == 1) {
+        // one cloud: the whole block reduces its partial boxes
+        float r[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+        uint64_t cnt = 0;
+#pragma unroll 4
+        for (int b = threadIdx.x; b < per_frame; b += kBlock) {
+            const float *q = partials + (size_t)b * 8;
+            for (int a = 0; a < 3; ++a) r[a] = fminf(r[a], q[a]);
+            for (int a = 3; a < 6; ++a) r[a] = fmaxf(r[a], q[a]);
+            cnt += __float_as_uint(q[6]);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            for (int a = 0; a < 3; ++a) r[a] = fminf(r[a], __shfl_xor(r[a], o));
+            for (int a = 3; a < 6; ++a) r[a] = fmaxf(r[a], __shfl_xor(r[a], o));
+            cnt += __shfl_xor(cnt, o);
+        }
+        __shared__ float s_r[kBlock / 64][6];
+        __shared__ uint64_t s_c[kBlock / 64];
+        if (lane == 0) {
+            for (int a = 0; a < 6; ++a) s_r[wave][a] = r[a];
+            s_c[wave] = cnt;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < kBlock / 64; ++w) {
+                for (int a = 0; a < 3; ++a) r[a] = fminf(r[a], s_r[w][a]);
+                for (int a = 3; a < 6; ++a) r[a] = fmaxf(r[a], s_r[w][a]);
+                cnt += s_c[w];
+            }
+            plan_frame(0, r, cnt, frames, nframes, n, offs, d_arr, min_arr, max_arr, d_one,
+                       min_one, max_one, &s_bad);
+        }
+    } else if (per_frame <= 16) {
         // many frames, few partial boxes each: one thread per frame
         for (int f = threadIdx.x; f < nframes; f += kBlock) {
             float r[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};

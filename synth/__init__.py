@@ -16,6 +16,7 @@ from .clouds import (  # noqa: F401
     chain_cloud,
     blob_lattice,
     lidar_batch,
+    serve_trace,
     make_batch_config,
     CONFIGS,
     make_config,

@@ -496,6 +496,26 @@ def lidar_batch(n_frames: int = 64, n_lo: int = 20000, n_hi: int = 200000,
     return frames, [float(ds[int(k)]) for k in dsel]
 
 
+def serve_trace(n_requests: int = 10000, rate: float = 400.0, pool: int = 512,
+                n_lo: int = 5000, n_hi: int = 500000, ds=(0.2, 0.5), seed: int = 5):
+    """A request stream for the serving engine.
+
+    Returns (frames, arrivals, frame_of, d_of): a pool of ``pool`` seeded
+    LiDAR frames with log-uniform point counts in [n_lo, n_hi]; Poisson
+    arrival times (seconds, exponential gaps of mean 1/rate); for every
+    request the pool frame it carries (drawn with replacement) and its d
+    (uniform over ``ds``).
+    """
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0x7365]))
+    counts = np.rint(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), pool))).astype(np.int64)
+    seeds = rng.integers(0, 2**31 - 1, pool)
+    frames = [lidar_frame(n=int(counts[b]), seed=int(seeds[b])) for b in range(pool)]
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_requests))
+    frame_of = rng.integers(0, pool, n_requests)
+    d_of = np.asarray(ds, dtype=np.float64)[rng.integers(0, len(ds), n_requests)]
+    return frames, arrivals, frame_of, d_of
+
+
 # --------------------------------------------------------------------------
 # named configurations
 # --------------------------------------------------------------------------

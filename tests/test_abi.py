@@ -118,3 +118,25 @@ def test_batch_workspace_bytes(fec):
     assert a == fec.workspace_bytes(1_000_000)
     assert a < b < a + 8 * 1_000_000
     assert fec.batch_workspace_bytes(0, 5) > 0
+
+
+def test_server_host_side_checks(fec):
+    lib = fec.raw_lib()
+    h = ctypes.c_void_p()
+    assert lib.fec_server_create(1 << 30, 0, 8, ctypes.byref(h)) == fec.FEC_EINVAL
+    assert lib.fec_server_create(1 << 30, 65, 8, ctypes.byref(h)) == fec.FEC_EINVAL
+    assert lib.fec_server_create(1 << 30, 2, 0, ctypes.byref(h)) == fec.FEC_EINVAL
+    assert lib.fec_server_create(1 << 30, 2, 1025, ctypes.byref(h)) == fec.FEC_EINVAL
+    assert lib.fec_server_create(1 << 30, 2, 8, None) == fec.FEC_EINVAL
+    t = ctypes.c_int64()
+    assert lib.fec_server_submit(None, None, 0, ctypes.c_float(0.3), 1, 2, None,
+                                 ctypes.byref(t)) == fec.FEC_EINVAL
+    assert lib.fec_server_pump(None, 0) == fec.FEC_EINVAL
+    assert lib.fec_server_poll(None, None, None, None, 4) == fec.FEC_EINVAL
+    assert lib.fec_server_slot_points(None) == 0
+    lib.fec_server_destroy(None)
+    # slot footprint: linear in points, grows with frames
+    a, b = fec.raw_lib().fec_server_slot_bytes(1_000_000, 64), lib.fec_server_slot_bytes(
+        2_000_000, 64)
+    assert 0 < a < b and lib.fec_server_slot_bytes(0, 8) == 0
+    assert lib.fec_server_slot_bytes(1000, 1025) == 0
