@@ -172,6 +172,24 @@ def bench_batch(args) -> None:
     if ks != ks_seq or not torch.equal(labels, labels_seq):
         raise SystemExit("bench: batched and per-frame results differ")
 
+    # the same call captured once in a graph and replayed (kernels only)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fec.cluster_batch_async(xyz, offs, d_t, lo_t, hi_t, labels=labels, k_out=kdev,
+                                workspace=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        fec.cluster_batch_async(xyz, offs, d_t, lo_t, hi_t, labels=labels, k_out=kdev,
+                                workspace=ws)
+    graph.replay()
+    torch.cuda.synchronize()
+    if kdev.cpu().tolist() != ks or not torch.equal(labels, labels_seq):
+        raise SystemExit("bench: graph replay differs from the eager call")
+    graph_ms = timed(graph.replay, args.steps)
+
     fec.profile_reset()
     fec.profile_enable()
     step()
@@ -204,6 +222,7 @@ def bench_batch(args) -> None:
                    "clusters_kept": int(sum(ks))},
         "sequential": {"ms_per_batch": seq_ms, "frames_per_s": nf / (seq_ms * 1e-3),
                        "speedup": seq_ms / ms_per_step},
+        "graph_replay": {"ms_per_batch": graph_ms, "frames_per_s": nf / (graph_ms * 1e-3)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dominant,
                      "avg_launch_ms": avg_launch_ms, "alg_bytes_per_launch": bytes_per_launch},

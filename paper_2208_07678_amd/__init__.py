@@ -263,6 +263,9 @@ def cluster_batch_async(xyz, offsets, d, min_size=1, max_size=2**31 - 1, *, labe
     d_t = _per_frame(d, nframes, torch.float32, dev)
     lo_t = _per_frame(min_size, nframes, torch.int32, dev)
     hi_t = _per_frame(max_size, nframes, torch.int32, dev)
+    # argument tensors made here (not the caller's) must outlive the launch
+    made = [t for t, src in ((offs, offsets), (d_t, d), (lo_t, min_size), (hi_t, max_size))
+            if t is not src]
     if labels is None:
         labels = torch.empty(n, dtype=torch.int32, device=dev)
     if k_out is None:
@@ -281,8 +284,7 @@ def cluster_batch_async(xyz, offsets, d, min_size=1, max_size=2**31 - 1, *, labe
             ctypes.c_void_p(stream.cuda_stream))
     if rc != FEC_OK:
         _raise(rc)
-    # keep the argument tensors alive until the stream has used them
-    for t in (offs, d_t, lo_t, hi_t):
+    for t in made:
         t.record_stream(stream)
     return labels, k_out, workspace
 

@@ -193,3 +193,52 @@ def test_batch_is_repeatable_and_reuses_workspace():
     assert np.array_equal(l2.cpu().numpy(), l1[: int(offs[5])]) and k2 == k1[:5]
     l3, k3 = fec.cluster_batch(xyz, offs, ds, mn, mx, workspace=ws)
     assert np.array_equal(l3.cpu().numpy(), l1) and k3 == k1
+
+
+def test_batch_call_captured_in_a_graph_replays_exactly():
+    # the batched call enqueues kernels only (no memset, no sync, no host
+    # read), so it can be captured once and replayed on new point data of
+    # the same sizes; every replay, with eager work in between, must equal
+    # an eager call
+    import torch
+
+    import paper_2208_07678_amd as fec
+
+    frames, ds, mn, mx = synth.make_batch_config("batch64", n_frames=10, seed=12)
+    dev = torch.device("cuda:0")
+    xyz, offs = fec.pack_frames([torch.from_numpy(f).to(dev) for f in frames])
+    nf = len(frames)
+    n = xyz.shape[0]
+    d_t = torch.tensor(ds, dtype=torch.float32, device=dev)
+    lo_t = torch.full((nf,), mn, dtype=torch.int32, device=dev)
+    hi_t = torch.full((nf,), mx, dtype=torch.int32, device=dev)
+    static_x = xyz.clone()
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    k_out = torch.empty(nf, dtype=torch.int32, device=dev)
+    ws = fec.new_batch_workspace(n, nf, dev)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fec.cluster_batch_async(static_x, offs, d_t, lo_t, hi_t, labels=labels, k_out=k_out,
+                                workspace=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    say("graph capture")
+    with torch.cuda.graph(graph):
+        fec.cluster_batch_async(static_x, offs, d_t, lo_t, hi_t, labels=labels, k_out=k_out,
+                                workspace=ws)
+    torch.cuda.synchronize()
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    for r in range(4):
+        shift = (torch.rand((n, 3), generator=gen) * 0.05).to(dev)
+        newx = (xyz + shift).contiguous()
+        static_x.copy_(newx)
+        say("graph replay", r)
+        graph.replay()
+        torch.cuda.synchronize()
+        got, gk = labels.cpu().numpy(), k_out.cpu().tolist()
+        want, wk = fec.cluster_batch(newx, offs, ds, mn, mx)
+        torch.cuda.synchronize()
+        assert np.array_equal(got, want.cpu().numpy()), "replay %d" % r
+        assert gk == wk, (r, gk, wk)
