@@ -59,6 +59,10 @@ def _load():
     lib.oracle_fec.argtypes = [f32p, ctypes.c_int64, ctypes.c_float, ctypes.c_int32,
                                ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
     lib.oracle_fec.restype = ctypes.c_int64
+    lib.oracle_fec_ex.argtypes = [f32p, ctypes.c_int64, ctypes.c_float, ctypes.c_int32,
+                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                  ctypes.c_void_p]
+    lib.oracle_fec_ex.restype = ctypes.c_int64
     lib.oracle_index_new.argtypes = [f32p, ctypes.c_int64, ctypes.c_float]
     lib.oracle_index_new.restype = ctypes.c_void_p
     lib.oracle_index_free.argtypes = [ctypes.c_void_p]
@@ -85,13 +89,19 @@ def _as_xyz(xyz) -> np.ndarray:
     return a
 
 
-def fec(xyz, d: float, min_size: int = 1, max_size: int = 2**31 - 1, flags: int = 0):
-    """Canonical FEC labels (int32 [n]) and the number of kept clusters."""
+def fec(xyz, d: float, min_size: int = 1, max_size: int = 2**31 - 1, flags: int = 0,
+        th_max: int = 0):
+    """Canonical FEC labels (int32 [n]) and the number of kept clusters.
+
+    ``flags`` and ``th_max`` (> 0: keep only the th_max nearest neighbours of
+    each visited point, Alg. 1's cap) select fidelity variants of Alg. 1 for
+    measuring their effect; the defaults are the exact clustering.
+    """
     a = _as_xyz(xyz)
     n = a.shape[0]
     out = np.empty(n, dtype=np.int32)
-    k = _load().oracle_fec(a.ctypes.data, n, ctypes.c_float(d), int(min_size),
-                           int(max_size), int(flags), out.ctypes.data)
+    k = _load().oracle_fec_ex(a.ctypes.data, n, ctypes.c_float(d), int(min_size),
+                              int(max_size), int(flags), int(th_max), out.ctypes.data)
     if k < 0:
         raise ValueError("oracle_fec rejected its arguments")
     return out, int(k)

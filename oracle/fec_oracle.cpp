@@ -25,7 +25,9 @@
 //   - every point is visited, including already-labelled ones (the printed
 //     "only if unlabelled" test splits some clusters, see the 4-point chain
 //     test);
-//   - the neighbour cap Th_max is unlimited;
+//   - the neighbour cap Th_max is unlimited (a capped variant, which keeps
+//     the Th_max nearest neighbours of p_i besides p_i itself, ties by index,
+//     exists for measuring its effect only);
 //   - unlabelled neighbours receive the minimum label (the printed merge
 //     loop only handles larger labels, which would leave every label 0);
 //   - the neighbour set of p_i contains p_i itself;
@@ -174,10 +176,21 @@ struct KdTree {
 // ---------------------------------------------------------------- Alg. 1
 enum : int32_t { kLiteralScan = 1, kSkipLabelled = 2 };
 
+// Binary32 squared distance in the predicate's order (for the capped
+// variant's nearest-first choice).
+inline float sq_dist(const float *a, const float *b) {
+    float dx = a[0] - b[0];
+    float dy = a[1] - b[1];
+    float dz = a[2] - b[2];
+    float s = dx * dx + dy * dy;
+    return s + dz * dz;
+}
+
 // Runs the point-wise loop over points 0..steps-1 and writes the label
-// value (0 = unlabelled, segment labels from 1) of every point.
+// value (0 = unlabelled, segment labels from 1) of every point.  th_max > 0
+// caps FindNeighbor at the th_max nearest neighbours besides p_i.
 void fec_loop(const float *xyz, int64_t n, float d, int64_t steps, int32_t flags,
-              int64_t *lab_out) {
+              int64_t *lab_out, int64_t th_max = 0) {
     KdTree tree(xyz, n, d);
     const bool literal = (flags & kLiteralScan) != 0;
     const bool skip = (flags & kSkipLabelled) != 0;
@@ -236,6 +249,14 @@ void fec_loop(const float *xyz, int64_t n, float d, int64_t steps, int32_t flags
         nn.clear();
         nn.push_back(i);
         tree.radius(xyz + 3 * i, [&](int64_t j) { if (j != i) nn.push_back(j); });
+        if (th_max > 0 && (int64_t)nn.size() - 1 > th_max) {
+            const float *q = xyz + 3 * i;
+            std::sort(nn.begin() + 1, nn.end(), [&](int64_t u, int64_t v) {
+                const float su = sq_dist(q, xyz + 3 * u), sv = sq_dist(q, xyz + 3 * v);
+                return su < sv || (su == sv && u < v);
+            });
+            nn.resize((size_t)th_max + 1);
+        }
         int64_t m = seg;
         for (int64_t j : nn) {
             int64_t l = label(j);
@@ -275,13 +296,14 @@ int32_t oracle_fec_raw(const float *xyz, int64_t n, float d, int64_t steps, int3
 
 // Full clustering: canonical labels (smallest member index, -1 when the
 // cluster size is outside [min_size, max_size]).  Returns the number of
-// kept clusters, or -1 on bad arguments.
-int64_t oracle_fec(const float *xyz, int64_t n, float d, int32_t min_size, int32_t max_size,
-                   int32_t flags, int32_t *labels_out) {
-    if (n < 0 || !d_ok(d) || min_size > max_size) return -1;
+// kept clusters, or -1 on bad arguments.  th_max > 0: the capped variant
+// (measurement only).
+int64_t oracle_fec_ex(const float *xyz, int64_t n, float d, int32_t min_size, int32_t max_size,
+                      int32_t flags, int64_t th_max, int32_t *labels_out) {
+    if (n < 0 || !d_ok(d) || min_size > max_size || th_max < 0) return -1;
     if (n == 0) return 0;
     std::vector<int64_t> lab(n);
-    fec_loop(xyz, n, d, n, flags, lab.data());
+    fec_loop(xyz, n, d, n, flags, lab.data(), th_max);
     // canonicalise: smallest index per label value, and cluster sizes
     std::vector<int64_t> first(n + 2, -1), size(n + 2, 0);
     for (int64_t i = 0; i < n; ++i) {
@@ -298,6 +320,12 @@ int64_t oracle_fec(const float *xyz, int64_t n, float d, int32_t min_size, int32
         labels_out[i] = (size[l] >= lo && size[l] <= max_size) ? (int32_t)first[l] : -1;
     }
     return k;
+}
+
+// Full clustering as Alg. 1 with the readings above (no cap).
+int64_t oracle_fec(const float *xyz, int64_t n, float d, int32_t min_size, int32_t max_size,
+                   int32_t flags, int32_t *labels_out) {
+    return oracle_fec_ex(xyz, n, d, min_size, max_size, flags, 0, labels_out);
 }
 
 // ------------------------------------------------------------ index queries
