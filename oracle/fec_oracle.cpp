@@ -178,12 +178,10 @@ enum : int32_t { kLiteralScan = 1, kSkipLabelled = 2 };
 
 // Binary32 squared distance in the predicate's order (for the capped
 // variant's nearest-first choice).
-inline float sq_dist(const float *a, const float *b) {
-    float dx = a[0] - b[0];
-    float dy = a[1] - b[1];
-    float dz = a[2] - b[2];
-    float s = dx * dx + dy * dy;
-    return s + dz * dz;
+inline float sq_dist(const float *p, const float *q) {
+    const float ex = p[0] - q[0], ey = p[1] - q[1], ez = p[2] - q[2];
+    const float t = ex * ex + ey * ey;
+    return t + ez * ez;
 }
 
 // Runs the point-wise loop over points 0..steps-1 and writes the label
