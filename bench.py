@@ -357,13 +357,79 @@ def bench_serve(args) -> None:
     print(json.dumps(out), flush=True)
 
 
+def bench_sweep(args) -> None:
+    """The paper's synthetic sweeps (voxel clusters): time per call and AP of
+    Eq. (2) against the generator's ground truth for every configuration, the
+    oracle timed beside it where the cloud has at most 400,000 points (one
+    JSON line)."""
+    import numpy as np
+    import torch
+
+    import paper_2208_07678_amd as fec
+    import synth
+    from paper_2208_07678_amd.metrics import average_precision
+
+    dev = torch.device("cuda:0")
+    d = synth.SWEEP_D
+    rows = []
+    for exp, nc, m, sub in synth.SWEEPS:
+        xyz, gt = synth.voxel_clusters(nc, m, subclusters=sub, seed=7)
+        n = xyz.shape[0]
+        x = torch.from_numpy(xyz).to(dev)
+        labels = torch.empty(n, dtype=torch.int32, device=dev)
+        kdev = torch.empty(1, dtype=torch.int32, device=dev)
+        ws = fec.new_workspace(n, dev)
+        stream = torch.cuda.current_stream(dev)
+        for _ in range(2):
+            fec.cluster_async(x, d, 1, n, labels=labels, k_out=kdev, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fec.cluster_async(x, d, 1, n, labels=labels, k_out=kdev, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        lab = labels.cpu().numpy()
+        row = {"experiment": exp, "clusters": nc, "density": m, "subclusters": sub, "n": n,
+               "gpu_ms": ms, "points_per_s": n / (ms * 1e-3), "kept": int(kdev.item()),
+               "ap": average_precision(lab, gt)}
+        if args.cpu_frames > 0 and n <= 400000 and exp.startswith(("E2", "E3")):
+            import oracle
+            t0 = time.perf_counter()
+            want, _ = oracle.fec(xyz, d, 1, n)
+            row["oracle_s"] = time.perf_counter() - t0
+            row["oracle_equal"] = bool(np.array_equal(want, lab))
+        rows.append(row)
+        print("bench: %s clusters=%d density=%d sub=%d n=%d %.3f ms AP %.4f" % (
+            exp, nc, m, sub, n, ms, row["ap"]), file=sys.stderr, flush=True)
+    big = max(rows, key=lambda r: r["n"])
+    out = {
+        "metric": "points/s on the synthetic voxel-cluster sweeps (largest configuration)",
+        "value": big["points_per_s"],
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 2,
+        "ms_per_step": big["gpu_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sweep", "d": d, "voxel": 1.0, "configs": len(rows)},
+        "sweep": rows,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="map27m",
-                    choices=["map27m", "lidar120k", "blobs20k", "batch64", "serve"])
+                    choices=["map27m", "lidar120k", "blobs20k", "batch64", "serve", "sweep"])
     ap.add_argument("--requests", type=int, default=10000, help="serve: requests in the trace")
     ap.add_argument("--rate", type=float, default=400.0, help="serve: Poisson arrivals per s")
     ap.add_argument("--pool", type=int, default=512, help="serve: distinct frames in the pool")
@@ -391,6 +457,9 @@ def main():
         return
     if args.workload == "serve":
         bench_serve(args)
+        return
+    if args.workload == "sweep":
+        bench_sweep(args)
         return
 
     import numpy as np  # noqa: F401

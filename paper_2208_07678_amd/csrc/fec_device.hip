@@ -1220,19 +1220,59 @@ __device__ __forceinline__ bool any_joined_1(const float4 *__restrict__ spts, ui
 // The points of B are read four at a time (independent loads in flight
 // together); an index past the end re-reads B's last point, which changes
 // nothing.
+//
+// Pairs of large cells that are not joined at once (cells across an empty
+// gap, the two sides of a thin wall) would cost |A| x |B| tests in one lane.
+// After two rows, the bounding box of B's points is taken, and a point a of
+// A is skipped when its binary32 distance to that box already fails the
+// predicate.  The box test is exact, not a heuristic: with gx = fl(lo_x -
+// a_x) (or fl(a_x - hi_x), or 0 inside), every b has |fl(a_x - b_x)| >= gx,
+// because rounding is monotone and lo_x, hi_x are coordinates of points of
+// B; the squares and the two sums are monotone too, so every pair's computed
+// s is at least the box's, and a box value >= fl(d*d) rules out every pair.
+__device__ __forceinline__ bool any_joined_row(const float4 &pa, const float4 *__restrict__ spts,
+                                               uint32_t sB, uint32_t eB, float d2) {
+    for (uint32_t b = sB; b < eB; b += 4) {
+        float4 q[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) q[j] = spts[b + j < eB ? b + j : eB - 1];
+        bool hit = false;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) hit |= joined(pa.x, pa.y, pa.z, q[j], d2);
+        if (hit) return true;
+    }
+    return false;
+}
+
 __device__ __forceinline__ bool any_joined(const float4 *__restrict__ spts, uint32_t sA,
                                            uint32_t eA, uint32_t sB, uint32_t eB, float d2) {
-    for (uint32_t a = sA; a < eA; ++a) {
-        const float4 pa = spts[a];
-        for (uint32_t b = sB; b < eB; b += 4) {
-            float4 q[4];
+#pragma clang fp contract(off)
+    const uint32_t plain = (eA - sA) * (eB - sB) <= 64 ? eA : (sA + 2 < eA ? sA + 2 : eA);
+    uint32_t a = sA;
+    for (; a < plain; ++a)
+        if (any_joined_row(spts[a], spts, sB, eB, d2)) return true;
+    if (a >= eA) return false;
+    float lx = INFINITY, ly = INFINITY, lz = INFINITY;
+    float hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
+    for (uint32_t b = sB; b < eB; b += 4) {
+        float4 q[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) q[j] = spts[b + j < eB ? b + j : eB - 1];
-            bool hit = false;
+        for (int j = 0; j < 4; ++j) q[j] = spts[b + j < eB ? b + j : eB - 1];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) hit |= joined(pa.x, pa.y, pa.z, q[j], d2);
-            if (hit) return true;
+        for (int j = 0; j < 4; ++j) {
+            lx = fminf(lx, q[j].x); ly = fminf(ly, q[j].y); lz = fminf(lz, q[j].z);
+            hx = fmaxf(hx, q[j].x); hy = fmaxf(hy, q[j].y); hz = fmaxf(hz, q[j].z);
         }
+    }
+    for (; a < eA; ++a) {
+        const float4 pa = spts[a];
+        const float gx = fmaxf(fmaxf(lx - pa.x, pa.x - hx), 0.0f);
+        const float gy = fmaxf(fmaxf(ly - pa.y, pa.y - hy), 0.0f);
+        const float gz = fmaxf(fmaxf(lz - pa.z, pa.z - hz), 0.0f);
+        float sb = gx * gx + gy * gy;
+        sb = sb + gz * gz;
+        if (!(sb < d2)) continue;
+        if (any_joined_row(pa, spts, sB, eB, d2)) return true;
     }
     return false;
 }

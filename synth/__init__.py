@@ -17,6 +17,9 @@ from .clouds import (  # noqa: F401
     blob_lattice,
     lidar_batch,
     serve_trace,
+    voxel_clusters,
+    SWEEPS,
+    SWEEP_D,
     make_batch_config,
     CONFIGS,
     make_config,

@@ -516,6 +516,61 @@ def serve_trace(n_requests: int = 10000, rate: float = 400.0, pool: int = 512,
     return frames, arrivals, frame_of, d_of
 
 
+def voxel_clusters(n_clusters: int, density: int, subclusters: int = 0, voxel: float = 1.0,
+                   seed: int = 0):
+    """Synthetic clusters in the manner of the paper's synthetic experiments.
+
+    Space is divided into cubic voxels of side ``voxel``; ``n_clusters``
+    voxels are picked at random among the sites of a lattice of pitch two
+    voxels (so an empty voxel separates any two clusters) and each is filled
+    with ``density`` points: evenly (a random subset of a k x k x k lattice
+    inside the voxel, k = ceil(density^(1/3))) when ``subclusters`` is 0,
+    else around ``subclusters`` Gaussian sub-cluster centres (uniform in the
+    voxel's middle 70 %, sigma = voxel / 8, clipped to the voxel).  The point
+    order is shuffled.  Returns (xyz float32 [n_clusters * density, 3],
+    ground-truth cluster id int32 [n]).
+    """
+    rng = np.random.default_rng(np.random.SeedSequence([seed, n_clusters, density,
+                                                        subclusters, 0x766F]))
+    L = 1
+    while L ** 3 < 2 * n_clusters:
+        L += 1
+    sites = rng.choice(L ** 3, size=n_clusters, replace=False)
+    corner = np.stack(np.unravel_index(sites, (L, L, L)), 1).astype(np.float64) * 2.0 * voxel
+    m = int(density)
+    if subclusters <= 0:
+        k = 1
+        while k ** 3 < m:
+            k += 1
+        g = (np.arange(k, dtype=np.float64) + 0.5) * voxel / k
+        lat = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+        pick = np.argsort(rng.random((n_clusters, k ** 3)), axis=1)[:, :m]
+        pts = corner[:, None, :] + lat[pick]
+    else:
+        centres = corner[:, None, :] + rng.uniform(0.15, 0.85, (n_clusters, subclusters, 3)) * voxel
+        which = rng.integers(0, subclusters, (n_clusters, m))
+        pts = np.take_along_axis(centres, which[..., None], axis=1)
+        pts = pts + rng.normal(0.0, voxel / 8.0, (n_clusters, m, 3))
+        lo = corner[:, None, :]
+        pts = np.clip(pts, lo, lo + voxel * (1.0 - 1e-6))
+    gt = np.repeat(np.arange(n_clusters, dtype=np.int32), m)
+    order = rng.permutation(n_clusters * m)
+    xyz = pts.reshape(-1, 3)[order].astype(np.float32)
+    return np.ascontiguousarray(xyz), gt[order]
+
+
+# The synthetic sweeps: (experiment, n_clusters, density, subclusters), d = 0.9 voxel.
+SWEEP_D = 0.9
+SWEEPS = (
+    [("E1 density x clusters", c, m, 0) for c in (100, 700, 1300, 1900, 2200)
+     for m in (10, 100, 200, 300, 400, 500)]
+    + [("E2 clusters at density 200", c, 200, 0) for c in (100, 400, 700, 1000, 1300, 1600, 1900)]
+    + [("E3 Gaussian sub-clusters", 1000, 200, s) for s in (1, 2, 4, 8, 16)]
+    + [("E4 clusters and density together", c, m, 0)
+       for c, m in ((100, 10), (500, 100), (1000, 200), (1600, 350), (2200, 500))]
+)
+
+
 # --------------------------------------------------------------------------
 # named configurations
 # --------------------------------------------------------------------------
