@@ -323,6 +323,10 @@ class Server:
             raise FecError(rc, "fec_server_create failed")
         self._h = h
         self._live = {}   # ticket -> (xyz, labels) kept alive until done
+        self._cap = 4096  # poll buffers, allocated once
+        self._tk = (ctypes.c_int64 * self._cap)()
+        self._kk = (ctypes.c_int32 * self._cap)()
+        self._lat = (ctypes.c_double * self._cap)()
 
     @property
     def slot_points(self) -> int:
@@ -352,9 +356,8 @@ class Server:
         return rc
 
     def poll(self, max_items: int = 4096):
-        tk = (ctypes.c_int64 * max_items)()
-        kk = (ctypes.c_int32 * max_items)()
-        lat = (ctypes.c_double * max_items)()
+        max_items = min(int(max_items), self._cap)
+        tk, kk, lat = self._tk, self._kk, self._lat
         c = _load().fec_server_poll(self._h, tk, kk, lat, max_items)
         out = []
         for i in range(c):

@@ -15,7 +15,8 @@
 // offsets, d, bounds, caller pointers), a gather kernel that packs the
 // requests' points into the slot, the batched pipeline, a scatter kernel
 // that writes each request's labels to the caller's buffer, and a copy of
-// the kept counts back to pinned host memory, followed by an event.
+// the kept counts back to pinned host memory, followed by an event.  A batch
+// of one request runs the single-cloud pipeline on the caller's buffers.
 
 #include "../../include/fec.h"
 #include "fec_internal.h"
@@ -225,6 +226,39 @@ int32_t launch(fec_server *S, Slot &s) {
     }
     if (batch.empty()) return 0;
     const int32_t F = (int32_t)batch.size();
+    if (F == 1 && batch[0].n > 0) {
+        // a lone request runs the single-cloud pipeline on the caller's own
+        // buffers: no table, gather or scatter (the common case at low load)
+        const Req &r = batch[0];
+        const fec::Layout L1 = fec::make_layout(r.n, 1);
+        fec::CallArgs a{};
+        a.xyz = r.xyz;
+        a.n = r.n;
+        a.nframes = 1;
+        a.d = r.d;
+        a.min_size = r.min_size;
+        a.max_size = r.max_size;
+        a.labels_out = r.labels;
+        a.k_out = s.k_dev;
+        hipError_t e = L1.total <= s.ws_bytes ? fec::launch_pipeline(a, s.ws, L1, s.stream, nullptr)
+                                              : hipErrorInvalidValue;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s.k_host, s.k_dev, sizeof(int32_t), hipMemcpyDeviceToHost,
+                               s.stream);
+        if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
+        if (e != hipSuccess) {
+            S->error = FEC_EDEVICE;
+            return FEC_EDEVICE;
+        }
+        s.reqs = std::move(batch);
+        s.busy = true;
+        ++S->n_batches;
+        S->max_batch_frames = std::max<int64_t>(S->max_batch_frames, 1);
+        int64_t busy = 0;
+        for (auto &q : S->slots) busy += q.busy ? 1 : 0;
+        S->max_in_flight = std::max(S->max_in_flight, busy);
+        return 1;
+    }
     const fec::Layout L = fec::make_layout(pts, F);
     if (L.total > s.ws_bytes) {  // cannot happen with the slot sizing; refuse loudly
         for (auto it = batch.rbegin(); it != batch.rend(); ++it) S->queue.push_front(*it);
