@@ -439,6 +439,8 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=30,
                     help="map frames in the CPU-baseline sample (0 = skip)")
     ap.add_argument("--stages", action="store_true", help="also print a per-stage breakdown")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the launch shape with the autotuner before timing")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES, three times (the "
                          "known-size reference for scaling HBM byte counters), then exit")
@@ -485,6 +487,12 @@ def main():
 
     def step():
         fec.cluster_async(x, d, mn, mx, labels=labels, k_out=kdev, workspace=ws, stream=stream)
+
+    tuned = None
+    if args.autotune:
+        from paper_2208_07678_amd import tune
+        tuned = tune.autotune(x, d, mn, mx, steps=3)
+        print("bench: autotune %s" % json.dumps(tuned), file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         step()
@@ -559,7 +567,9 @@ def main():
                    "max_size": mx, "clusters_kept": k, "cells": stats.get("cells"),
                    "max_points_per_cell": stats.get("max_points_per_cell"),
                    "radix_passes": stats.get("radix_passes"),
-                   "work_cells": stats.get("work_cells")},
+                   "work_cells": stats.get("work_cells"),
+                   "launch_shape": list(fec.get_tuning()),
+                   "autotuned": tuned is not None},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

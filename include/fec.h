@@ -244,6 +244,16 @@ int32_t fec_profile_enable(uint64_t stage_mask);
 int32_t fec_profile_read(double *ms_total, int64_t *launches, int32_t max_stages);
 void fec_profile_reset(void);
 int32_t fec_stage_count(void);
+
+/*
+ * Launch shape (the autotuner's knobs; process-wide, applies to calls
+ * enqueued afterwards): the most blocks of the per-cell grid-stride kernels
+ * (default 4096) and of the per-point streaming kernels (default 4096); 0
+ * restores a default.  Labels and counts do not depend on them.  Returns
+ * FEC_OK, or FEC_EINVAL for values outside [0, 2^20].
+ */
+int32_t fec_tuning_set(int32_t cell_blocks, int32_t stream_blocks);
+int32_t fec_tuning_get(int32_t *cell_blocks, int32_t *stream_blocks);
 const char *fec_stage_name(int32_t stage);
 
 #ifdef __cplusplus

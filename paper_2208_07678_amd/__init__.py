@@ -63,6 +63,8 @@ def _load():
                                      vp], i32),
         "fec_batch_workspace_bytes": ([i64, i32], ctypes.c_size_t),
         "fec_server_slot_bytes": ([i64, i32], ctypes.c_size_t),
+        "fec_tuning_set": ([i32, i32], i32),
+        "fec_tuning_get": ([vp, vp], i32),
         "fec_server_create": ([ctypes.c_size_t, i32, i32, vp], i32),
         "fec_server_slot_points": ([vp], i64),
         "fec_server_submit": ([vp, vp, i64, f32, i32, i32, vp, vp], i32),
@@ -93,7 +95,8 @@ EXPORTED = [
     "fec_cluster", "fec_workspace_bytes", "fec_cluster_async", "fec_set_stream", "fec_release",
     "fec_cluster_batch_async", "fec_batch_workspace_bytes", "fec_server_slot_bytes",
     "fec_server_create", "fec_server_slot_points", "fec_server_submit", "fec_server_pump",
-    "fec_server_poll", "fec_server_stats", "fec_server_destroy",
+    "fec_server_poll", "fec_server_stats", "fec_server_destroy", "fec_tuning_set",
+    "fec_tuning_get",
     "fec_last_error", "fec_version", "fec_workspace_stats", "fec_profile_enable",
     "fec_profile_read", "fec_profile_reset", "fec_stage_count", "fec_stage_name",
 ]
@@ -192,6 +195,19 @@ def cluster(xyz, d: float, min_size: int = 1, max_size: int = 2**31 - 1, *,
     if k < 0:
         raise FecError(k, "device-side status %d" % k)
     return labels, k
+
+
+def set_tuning(cell_blocks: int = 0, stream_blocks: int = 0) -> None:
+    """Launch shape of later calls (0 = default); see ``paper_2208_07678_amd.tune``."""
+    rc = _load().fec_tuning_set(int(cell_blocks), int(stream_blocks))
+    if rc != FEC_OK:
+        _raise(rc)
+
+
+def get_tuning() -> tuple[int, int]:
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _load().fec_tuning_get(ctypes.byref(a), ctypes.byref(b))
+    return int(a.value), int(b.value)
 
 
 def batch_workspace_bytes(n_total: int, nframes: int) -> int:

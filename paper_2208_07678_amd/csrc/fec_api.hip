@@ -303,6 +303,22 @@ void fec_profile_reset(void) {
     }
 }
 
+int32_t fec_tuning_set(int32_t cell_blocks, int32_t stream_blocks) {
+    if (cell_blocks < 0 || stream_blocks < 0 || cell_blocks > (1 << 20) ||
+        stream_blocks > (1 << 20))
+        return fail(FEC_EINVAL, "tuning values outside [0, 2^20]");
+    fec::set_tuning({cell_blocks ? cell_blocks : fec::kDefaultCellBlocks,
+                     stream_blocks ? stream_blocks : fec::kDefaultStreamBlocks});
+    return ok();
+}
+
+int32_t fec_tuning_get(int32_t *cell_blocks, int32_t *stream_blocks) {
+    const fec::Tuning t = fec::tuning();
+    if (cell_blocks) *cell_blocks = t.cell_blocks;
+    if (stream_blocks) *stream_blocks = t.stream_blocks;
+    return ok();
+}
+
 int32_t fec_stage_count(void) { return fec::kNumStages; }
 
 const char *fec_stage_name(int32_t stage) { return fec::stage_name(stage); }

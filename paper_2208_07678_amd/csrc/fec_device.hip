@@ -33,6 +33,8 @@
 #include <float.h>
 #include <math.h>
 
+#include <atomic>
+
 namespace fec {
 
 // ------------------------------------------------------------------ helpers
@@ -2081,6 +2083,21 @@ __global__ __launch_bounds__(kBlock) void k_finish(const Params *__restrict__ P,
 
 // ------------------------------------------------------------------ host side
 
+namespace {
+std::atomic<int32_t> g_cell_blocks{kDefaultCellBlocks};
+std::atomic<int32_t> g_stream_blocks{kDefaultStreamBlocks};
+}  // namespace
+
+Tuning tuning() {
+    return Tuning{g_cell_blocks.load(std::memory_order_relaxed),
+                  g_stream_blocks.load(std::memory_order_relaxed)};
+}
+
+void set_tuning(Tuning t) {
+    g_cell_blocks.store(t.cell_blocks, std::memory_order_relaxed);
+    g_stream_blocks.store(t.stream_blocks, std::memory_order_relaxed);
+}
+
 const char *stage_name(int s) {
     static const char *names[kNumStages] = {
         "bbox",       "plan",      "keys",       "sort_hist",   "sort_scan",    "sort_scatter",
@@ -2127,8 +2144,11 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     const int64_t ntiles = L.ntiles;
     const int bbox_pf = L.bbox_per_frame;
     int64_t nb_pts = (n + kBlock - 1) / kBlock;
-    const int nb_stream = (int)(nb_pts > 8192 ? 8192 : (nb_pts < 1 ? 1 : nb_pts));
-    const int nb_cells = (int)(nb_pts > kCellBlocks ? kCellBlocks : (nb_pts < 1 ? 1 : nb_pts));
+    const Tuning tn = tuning();
+    const int nb_stream =
+        (int)(nb_pts > tn.stream_blocks ? tn.stream_blocks : (nb_pts < 1 ? 1 : nb_pts));
+    const int nb_cells =
+        (int)(nb_pts > tn.cell_blocks ? tn.cell_blocks : (nb_pts < 1 ? 1 : nb_pts));
     // key blocks per frame: one cloud takes the streaming grid; frames take
     // about one block per 2048 points of an average frame (each block flushes
     // a full digit histogram, so tiny blocks would cost more in flushes)

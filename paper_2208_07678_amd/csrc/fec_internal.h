@@ -221,6 +221,19 @@ struct CallArgs {
     int32_t *k_out;
 };
 
+// Launch shape of the grid-stride kernels, settable at run time (the
+// autotuner's knobs): blocks of the per-cell kernels (near / far shells,
+// compression, finalize) and of the per-point streaming kernels.  Results do
+// not depend on them.
+struct Tuning {
+    int32_t cell_blocks;
+    int32_t stream_blocks;
+};
+constexpr int32_t kDefaultCellBlocks = kCellBlocks;
+constexpr int32_t kDefaultStreamBlocks = 4096;
+Tuning tuning();
+void set_tuning(Tuning t);
+
 // Enqueues the whole pipeline.  Returns hipSuccess or the first launch error.
 hipError_t launch_pipeline(const CallArgs &a, void *ws, const Layout &L, hipStream_t stream,
                            Timer *timer);

@@ -140,3 +140,22 @@ def test_server_host_side_checks(fec):
         2_000_000, 64)
     assert 0 < a < b and lib.fec_server_slot_bytes(0, 8) == 0
     assert lib.fec_server_slot_bytes(1000, 1025) == 0
+
+
+def test_tuning_knobs_and_cache(fec, tmp_path):
+    from paper_2208_07678_amd import tune
+    assert fec.get_tuning() == (4096, 4096)
+    fec.set_tuning(1024, 8192)
+    assert fec.get_tuning() == (1024, 8192)
+    with pytest.raises(fec.FecError):
+        fec.set_tuning(-1, 0)
+    fec.set_tuning(0, 0)
+    assert fec.get_tuning() == (4096, 4096)
+    # cache round trip, keyed by arch and size bucket
+    p = str(tmp_path / "tune.json")
+    assert tune.lookup("gfx950", 27_000_000, p) is None
+    tune.record("gfx950", 27_000_000, (2048, 8192), 6.1, p)
+    assert tune.lookup("gfx950", 20_000_000, p) == (2048, 8192)    # same bucket (2^24)
+    assert tune.lookup("gfx950", 40_000_000, p) is None            # next bucket
+    assert tune.lookup("gfx942", 27_000_000, p) is None
+    assert tune.bucket(1) == 0 and tune.bucket(4096) == 12

@@ -242,3 +242,25 @@ def test_batch_call_captured_in_a_graph_replays_exactly():
         torch.cuda.synchronize()
         assert np.array_equal(got, want.cpu().numpy()), "replay %d" % r
         assert gk == wk, (r, gk, wk)
+
+
+def test_batch_with_a_wide_frame_uses_pairs_and_search():
+    # one frame at d = 1 mm over 100 m: the stacked key no longer fits beside
+    # the point index (pair mode) and the column key is too wide for a hash
+    # slot (binary search); the other frames must not notice
+    import paper_2208_07678_amd as fec
+    import torch
+
+    rng = np.random.default_rng(8)
+    centres = rng.uniform(0, 100, size=(300, 3))
+    wide = (np.repeat(centres, 10, axis=0) + rng.uniform(-3e-4, 3e-4, size=(3000, 3)))
+    wide = wide.astype(np.float32)[rng.permutation(3000)]
+    frames = [synth.blobs_cloud(n=4000, n_blobs=8, seed=5), wide,
+              synth.random_cloud(2000, extent=(5, 5, 1), seed=6)]
+    ds, mins, maxs = [0.4, 1e-3, 0.3], [1, 1, 2], [4000, 3000, 2000]
+    _check_batch(frames, ds, mins, maxs, "wide frame")
+    xyz, offs = fec.pack_frames([torch.from_numpy(f).to("cuda:0") for f in frames])
+    ws = fec.new_batch_workspace(xyz.shape[0], 3, xyz.device)
+    fec.cluster_batch(xyz, offs, ds, mins, maxs, workspace=ws)
+    st = fec.workspace_stats(ws)
+    assert st["key_bits"] + 13 > 64 and st["column_index"] == 0, st
