@@ -286,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ parti
     __shared__ int64_t s_tmp[kBlock / 64];
     __shared__ int32_t s_bad;
     const int wave = threadIdx.x >> 6, lane = __lane_id();
-    for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kBlock) (&P->hist[0][0])[i] = 0;
+
     if (threadIdx.x < 8) P->counters[threadIdx.x] = 0;
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
@@ -448,31 +448,26 @@ __device__ __forceinline__ uint64_t make_key(uint64_t cx, uint64_t cy, uint64_t 
 }
 
 // ------------------------------------------------------------- 3. keys
-// Packs (cell key << idx_bits) | point index and counts the radix digits of
-// every pass.  Block f * per_frame + j takes the j-th share of frame f; the
-// cell's x coordinate is offset by the frame's place in the stacked grid.
-// Points of a refused frame get the key of non-finite points (sorted last).
+// Packs (cell key << idx_bits) | point index.  Block f * per_frame + j takes
+// the j-th share of frame f; the cell's x coordinate is offset by the
+// frame's place in the stacked grid.  Points of a refused frame get the key
+// of non-finite points (sorted last).
 __global__ __launch_bounds__(kBlock) void k_keys(const float *__restrict__ xyz,
                                                  Params *__restrict__ P,
                                                  const Frame *__restrict__ frames, int per_frame,
                                                  uint64_t *__restrict__ keys,
                                                  uint32_t *__restrict__ vals) {
-    __shared__ uint32_t sh[kMaxPasses][kRadix];
     if (P->status != kStatusOk) return;
-    for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kBlock) (&sh[0][0])[i] = 0;
-    __syncthreads();
     const int f = blockIdx.x / per_frame, j = blockIdx.x % per_frame;
     const Frame *F = frames + f;
     const int64_t lo = F->off0, hi = F->off1;
     const bool accepted = F->status == kStatusOk;
-    const int np = P->npasses;
     const int ks = P->key_shift;
     const bool pair = P->pair_mode != 0;
     const double ox = F->ox, oy = F->oy, oz = F->oz, inv = F->inv_s;
     const int64_t NX = F->NX, NY = F->NY, NZ = F->NZ, xoff = F->xoff;
     const int by = P->by, bz = P->bz;
     const uint64_t invalid_key = 1ull << (P->bx + by + bz);
-    const int lane = __lane_id();
     for (int64_t i = lo + (int64_t)j * kBlock + threadIdx.x; i < hi;
          i += (int64_t)per_frame * kBlock) {
         const float x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
@@ -488,25 +483,8 @@ __global__ __launch_bounds__(kBlock) void k_keys(const float *__restrict__ xyz,
         } else {
             key = invalid_key;
         }
-        const uint64_t e = pair ? key : ((key << ks) | (uint64_t)i);
-        keys[i] = e;
+        keys[i] = pair ? key : ((key << ks) | (uint64_t)i);
         if (pair) vals[i] = (uint32_t)i;
-        const uint64_t act = __ballot(1);
-        const int leader = first_lane(act);
-        for (int p = 0; p < np; ++p) {
-            const uint32_t dg = (uint32_t)(e >> (ks + p * kRadixBits)) & (kRadix - 1);
-            const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
-            if (__ballot(dg == d0) == act) {
-                if (lane == leader) atomicAdd(&sh[p][d0], (uint32_t)__popcll(act));
-            } else {
-                atomicAdd(&sh[p][dg], 1u);
-            }
-        }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < np * kRadix; i += kBlock) {
-        const uint32_t v = (&sh[0][0])[i];
-        if (v) atomicAdd(&(&P->hist[0][0])[i], v);
     }
 }
 
@@ -514,9 +492,13 @@ __global__ __launch_bounds__(kBlock) void k_keys(const float *__restrict__ xyz,
 // Stable LSD radix sort of the packed (key, index) words, kRadixBits per
 // pass, reduce-then-scan: (1) each tile of kTile words counts its digits,
 // (2) one block per digit turns the per-tile counts (digit-major) into the
-// global position of that digit's first word in every tile, (3) each tile
+// position of every tile's run of that digit, counted from the digit's first
+// word, and the digit's total, (3) each tile
 // ranks its words stably, stages them in LDS in digit order and writes each
-// digit's run to its position.  Tiles are independent in every step.
+// digit's run to its position.  Tiles are independent in every step.  The
+// digits' global bases come from the per-digit totals of step (2), scanned
+// by every scatter block (256 values), so no earlier kernel has to count
+// digits over the whole array.
 
 // Digit and stable in-wave rank of item k of this wave (lanes with equal
 // digits are "peers"; the rank counts peers on lower lanes).
@@ -565,16 +547,16 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(const uint64_t *__restrict
 }
 
 // (2) one block per digit: exclusive scan of the digit's per-tile counts
-// plus the digit's global base (the counts of all smaller digits).
-__global__ __launch_bounds__(kBlock) void k_sort_scan(const Params *__restrict__ P, int pass,
+// (positions relative to the digit's first word) and the digit's total,
+// published for the scatter blocks, which add the digits' bases themselves.
+__global__ __launch_bounds__(kBlock) void k_sort_scan(Params *__restrict__ P, int pass,
                                                       int64_t ntiles, uint32_t *__restrict__ th) {
     if (pass >= P->npasses || P->status != kStatusOk) return;
     __shared__ uint32_t s_tmp[kBlock / 64];
     __shared__ uint32_t s_carry;
     const int d = blockIdx.x, tid = threadIdx.x;
     uint32_t tot;
-    const uint32_t hb = block_excl_scan(P->hist[pass][tid], s_tmp, tot);
-    if (tid == d) s_carry = hb;
+    if (tid == 0) s_carry = 0;
     __syncthreads();
     uint32_t *row = th + (int64_t)d * ntiles;
     for (int64_t c0 = 0; c0 < ntiles; c0 += kTile) {
@@ -600,6 +582,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scan(const Params *__restrict__
         if (tid == 0) s_carry = carry + tot;
         __syncthreads();
     }
+    if (tid == 0) P->hist[pass][d] = s_carry;
 }
 
 // (3) stable scatter of one tile.
@@ -619,7 +602,13 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const uint64_t *__restr
     const int tid = threadIdx.x, wave = tid >> 6, lane = __lane_id();
     for (int i = tid; i < (kBlock / 64) * kRadix; i += kBlock) (&s_cnt[0][0])[i] = 0;
     const int64_t tile = blockIdx.x;
-    s_base[tid] = th[(int64_t)tid * ntiles + tile];
+    {
+        // this tile's position within each digit, plus the digit's base (the
+        // totals of all smaller digits)
+        uint32_t tot;
+        const uint32_t base = block_excl_scan(P->hist[pass][tid], s_tmp, tot);
+        s_base[tid] = base + th[(int64_t)tid * ntiles + tile];
+    }
     __syncthreads();
     const int shift = P->key_shift + pass * kRadixBits;
     const bool pair = P->pair_mode != 0;

@@ -90,7 +90,7 @@ struct Params {
     uint64_t hmask;       // slots - 1
     uint64_t hcap;        // slots that fit in the dense index's memory (a power of two)
     unsigned long long counters[8];  // diagnostic event counts (counting builds only)
-    uint32_t hist[kMaxPasses][kRadix];
+    uint32_t hist[kMaxPasses][kRadix];   // digit totals of each pass
 };
 
 // ---------------------------------------------------------------- workspace
