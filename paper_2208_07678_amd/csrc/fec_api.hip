@@ -9,7 +9,6 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>

@@ -5,9 +5,13 @@
 // min/max size filter, labels = smallest member index.  The paper's serial
 // point-wise loop is replaced by a grid-based design:
 //
-//   bbox -> plan -> keys(+digit histograms) -> radix sort passes -> gather
-//   -> cell table -> column hash -> hook (near shell) -> compress
-//   -> hook (far shell) -> compress -> cluster sizes/ids -> labels
+//   bbox -> plan -> keys -> radix sort passes -> gather -> cell table
+//   -> column index (dense table, hash or search) -> runs -> hook (near
+//   shell) -> compress -> giant component / work list -> hook (far shell)
+//   -> compress -> cluster sizes/ids -> labels
+//
+// One call covers one cloud or a batch of frames: every frame has its own
+// grid, and the frames' grids are laid side by side along x (see k_plan).
 //
 // Grid.  Cells are cubes of side s = d (1 - 2^-10) / sqrt(3).  Any two points
 // of one cell are closer than s*sqrt(3) < d (with room for the rounding of
@@ -24,9 +28,10 @@
 // compression most of a dense surface is one component and the far shell
 // (offsets of 2) is mostly skipped by the root comparison.
 //
-// Determinism.  The union-find always hooks the larger root under the
-// smaller; the partition it reaches is the unique set of components, and the
-// labels (smallest original index per component) do not depend on timing.
+// Determinism.  The union-find always hooks the root of higher rank under
+// the other (rank: a fixed scramble of the cell id); the partition it
+// reaches is the unique set of components, and the labels (smallest
+// original index per component) do not depend on timing.
 
 #include "fec_internal.h"
 
