@@ -51,23 +51,41 @@ def _cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(frames: int):
+def cpu_baseline(frames: int, runs: int = 3):
+    """The oracle, single-threaded and pinned to one core, on the first
+    ``frames`` frames of the map: median of ``runs`` runs."""
     import numpy as np  # noqa: F401
 
     import oracle
     import synth
     xyz = synth.lidar_map(frames=list(range(frames)))
-    t0 = time.perf_counter()
-    _, k = oracle.fec(xyz, 0.2, 100, 5000000)
-    dt = time.perf_counter() - t0
+    pinned = None
+    try:
+        allowed = sorted(os.sched_getaffinity(0))
+        pinned = allowed[0]
+        os.sched_setaffinity(0, {pinned})
+    except (AttributeError, OSError):
+        allowed = None
+    times = []
+    try:
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            _, k = oracle.fec(xyz, 0.2, 100, 5000000)
+            times.append(time.perf_counter() - t0)
+    finally:
+        if allowed is not None:
+            os.sched_setaffinity(0, set(allowed))
+    dt = sorted(times)[len(times) // 2]
     return {
         "value": xyz.shape[0] / dt,
         "unit": "points/s",
         "cores": 1,
         "kind": "oracle",
         "sample": "first %d of 200 frames of the map (%d points), d=0.2, sizes 100..5e6; "
-                  "single-threaded C++ (Alg. 1 over a kd-tree), %.2f s, host %s, %d cores "
-                  "available" % (frames, xyz.shape[0], dt, _cpu_model(), os.cpu_count() or 0),
+                  "single-threaded C++ (Alg. 1 over a kd-tree) pinned to core %s, median of %d "
+                  "runs %.2f s, host %s, %d cores available" % (
+                      frames, xyz.shape[0], pinned, runs, dt, _cpu_model(),
+                      os.cpu_count() or 0),
         "seconds": dt,
         "clusters": k,
     }
@@ -93,19 +111,35 @@ def _source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None when there is none for it or the kernel sources changed since."""
+def _traffic_record():
     path = os.path.join(ROOT, "profiles", "traffic_map27m.json")
     try:
         with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha256") != _source_digest():
-        return None
-    k = rec.get("kernels", {}).get(kernel)
+    return rec if rec.get("source_sha256") == _source_digest() else None
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when there is none for it or the kernel sources changed since."""
+    rec = _traffic_record()
+    k = None if rec is None else rec.get("kernels", {}).get(kernel)
     return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def path_traffic(passes: int):
+    """Measured HBM bytes of one whole call on the map (every kernel, the
+    sort's kernels once per pass), or None (see measured_traffic)."""
+    rec = _traffic_record()
+    if rec is None:
+        return None
+    tot = 0
+    for st, k in rec.get("kernels", {}).items():
+        mult = passes if st.startswith("sort") else (2 if st == "compress" else 1)
+        tot += k["hbm_bytes_per_launch"] * mult
+    return tot
 
 
 def bench_batch(args) -> None:
@@ -525,6 +559,30 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = n / (ms_per_step * 1e-3)
 
+    # per-call times (events on the stream, outside the timed region), and
+    # the blocking form's wall time
+    import numpy as np
+    per_call = []
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        step()
+        e1.record(stream)
+        e1.synchronize()
+        per_call.append(e0.elapsed_time(e1))
+    blocking = []
+    for _ in range(3):
+        b0 = time.perf_counter()
+        fec.cluster(x, d, mn, mx, workspace=ws, labels=labels)
+        blocking.append((time.perf_counter() - b0) * 1e3)
+    call_ms = {"median": float(np.median(per_call)), "p99": float(np.percentile(per_call, 99)),
+               "blocking_median": float(np.median(blocking))}
+    kernel_ms = sum(v[0] for v in prof_all.values())
+    tb = path_traffic(stats.get("radix_passes") or 0)
+    path = {"kernel_ms": kernel_ms, "hbm_bytes": tb,
+            "hbm_GBps": None if tb is None else tb / (kernel_ms * 1e-3) / 1e9,
+            "frac": None if tb is None else tb / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
     avg_launch_ms = dom_ms / max(dom_launches, 1)
     if dominant in ALG_BYTES_PER_POINT:
         launches_per_step = dom_launches / args.steps
@@ -566,11 +624,14 @@ def main():
         "config": {"workload": args.workload, "n_points": n, "d": d, "min_size": mn,
                    "max_size": mx, "clusters_kept": k, "cells": stats.get("cells"),
                    "max_points_per_cell": stats.get("max_points_per_cell"),
+                   "mean_points_per_cell": n / max(stats.get("cells") or 1, 1),
                    "radix_passes": stats.get("radix_passes"),
                    "work_cells": stats.get("work_cells"),
                    "launch_shape": list(fec.get_tuning()),
                    "autotuned": tuned is not None},
         "roofline": roofline,
+        "call_ms": call_ms,
+        "path": path,
         "cpu_baseline": cpu,
     }
     if args.stages:
