@@ -1449,6 +1449,7 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
     const Grid g = grid_of(P);
     constexpr int kC = 4;
     constexpr int kCand = kC * kNearK + 1;
+    static_assert(kCand <= 32, "candidate masks are 32-bit");
     for (int64_t Ai = (int64_t)blockIdx.x * kBlock + threadIdx.x; Ai < M;
          Ai += (int64_t)gridDim.x * kBlock) {
         const int32_t A = (int32_t)Ai;
@@ -1753,6 +1754,8 @@ __global__ __launch_bounds__(kBlock) void k_hook_far(const float4 *__restrict__ 
     const Grid g = grid_of(P);
     constexpr int kG = 8;      // columns per group (loads issued together)
     constexpr int kK = 2;      // cells per column loaded up front
+    static_assert(kG * kK <= 32, "candidate masks are 32-bit");
+    static_assert(kG <= 32 && 24 % kG == 0, "groups cover the 24 columns");
     for (uint32_t wi = blockIdx.x * kBlock + threadIdx.x; wi < nwork; wi += gridDim.x * kBlock) {
         const int32_t A = (int32_t)work[wi];
         const uint64_t key = cell_key[A];
