@@ -457,13 +457,73 @@ def bench_sweep(args) -> None:
     print(json.dumps(out), flush=True)
 
 
+def bench_scale(args) -> None:
+    """Single-cloud calls on growing prefixes of the map (1 to 200 frames):
+    time per call and points/s, from the latency-bound to the throughput-bound
+    regime (one JSON line)."""
+    import numpy as np
+    import torch
+
+    import paper_2208_07678_amd as fec
+    import synth
+
+    xyz_all, d, mn, mx = synth.make_config("map27m")
+    per = xyz_all.shape[0] // 200
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    rows = []
+    for frames in (1, 2, 5, 10, 20, 50, 100, 200):
+        n = frames * per
+        x = torch.from_numpy(np.ascontiguousarray(xyz_all[:n])).to(dev)
+        labels = torch.empty(n, dtype=torch.int32, device=dev)
+        kdev = torch.empty(1, dtype=torch.int32, device=dev)
+        ws = fec.new_workspace(n, dev)
+        for _ in range(2):
+            fec.cluster_async(x, d, mn, mx, labels=labels, k_out=kdev, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fec.cluster_async(x, d, mn, mx, labels=labels, k_out=kdev, workspace=ws, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        rows.append({"frames": frames, "n": n, "ms_median": ms, "points_per_s": n / (ms * 1e-3),
+                     "kept": int(kdev.item())})
+        print("bench: %d frames n=%d %.3f ms" % (frames, n, ms), file=sys.stderr, flush=True)
+        del x, labels, ws
+    big = rows[-1]
+    out = {
+        "metric": "points/s clustered on map prefixes (largest = the whole map)",
+        "value": big["points_per_s"],
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 2,
+        "ms_per_step": big["ms_median"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "scale", "d": d, "min_size": mn, "max_size": mx},
+        "scale": rows,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="map27m",
-                    choices=["map27m", "lidar120k", "blobs20k", "batch64", "serve", "sweep"])
+                    choices=["map27m", "lidar120k", "blobs20k", "batch64", "serve", "sweep",
+                             "scale"])
     ap.add_argument("--requests", type=int, default=10000, help="serve: requests in the trace")
     ap.add_argument("--rate", type=float, default=400.0, help="serve: Poisson arrivals per s")
     ap.add_argument("--pool", type=int, default=512, help="serve: distinct frames in the pool")
@@ -496,6 +556,9 @@ def main():
         return
     if args.workload == "sweep":
         bench_sweep(args)
+        return
+    if args.workload == "scale":
+        bench_scale(args)
         return
 
     import numpy as np  # noqa: F401
