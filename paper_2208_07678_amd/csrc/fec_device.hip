@@ -1733,6 +1733,13 @@ __device__ __forceinline__ bool is_giant(const uint64_t *__restrict__ gbits, uin
     return (gbits[B >> 6] >> (B & 63)) & 1ull;
 }
 
+// Work lists shorter than this are cut into one task per column group
+// (a small cloud leaves most of the chip idle, and each lane's chain of
+// dependent loads sets the kernel's time); longer ones keep one task per
+// cell (the chip is full, and the tasks' repeated set-up would cost more).
+constexpr uint32_t kFarSplitBelow = 131072;
+
+template <bool kSplit>
 __global__ __launch_bounds__(kBlock) void k_hook_far(const float4 *__restrict__ spts,
                                                       const uint32_t *__restrict__ cell_start,
                                                       const uint64_t *__restrict__ cell_key,
@@ -1756,7 +1763,17 @@ __global__ __launch_bounds__(kBlock) void k_hook_far(const float4 *__restrict__ 
     constexpr int kK = 2;      // cells per column loaded up front
     static_assert(kG * kK <= 32, "candidate masks are 32-bit");
     static_assert(kG <= 32 && 24 % kG == 0, "groups cover the 24 columns");
-    for (uint32_t wi = blockIdx.x * kBlock + threadIdx.x; wi < nwork; wi += gridDim.x * kBlock) {
+    if ((nwork < kFarSplitBelow) != kSplit) return;  // the other instance's case
+    // kSplit: one task per (work cell, group of kG columns).  The groups of a
+    // cell are independent; a lane that walks all of them in turn carries
+    // one long chain of dependent loads (about 50 us per cell, measured).
+    constexpr uint32_t kGroups = 24 / kG;
+    constexpr uint32_t kTasks = kSplit ? kGroups : 1;
+    const uint64_t ntask = (uint64_t)nwork * kTasks;
+    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < ntask;
+         t += (uint64_t)gridDim.x * kBlock) {
+        const uint32_t wi = (uint32_t)(t / kTasks);
+        const int task = (int)(t % kTasks);
         const int32_t A = (int32_t)work[wi];
         const uint64_t key = cell_key[A];
         const uint64_t ck = key >> g.bz;
@@ -1776,22 +1793,25 @@ __global__ __launch_bounds__(kBlock) void k_hook_far(const float4 *__restrict__ 
             if (any_joined(spts, sA, eA, cell_start[B], cell_start[B + 1], d2))
                 ra = uf_link_roots(cpar, uf_find(cpar, ra), rb);
         };
-        // own column: the cells two steps down (if giant) and up
-        for (int32_t B = A - 1; B >= 0 && B >= A - 2; --B) {
+        // own column (first task of the cell): the cells two steps down (if
+        // giant) and up
+        for (int32_t B = A - 1; task == 0 && B >= 0 && B >= A - 2; --B) {
             const uint64_t kb = cell_key[B];
             const int64_t dz = cz - (int64_t)(kb & g.zmask);
             if ((kb >> g.bz) != ck || dz > 2) break;
             if (dz == 2 && is_giant(gbits, (uint32_t)B)) pair((uint32_t)B, cpar[B]);
         }
-        for (int32_t B = A + 1; B < M && B <= A + 2; ++B) {
+        for (int32_t B = A + 1; task == 0 && B < M && B <= A + 2; ++B) {
             const uint64_t kb = cell_key[B];
             const int64_t dz = (int64_t)(kb & g.zmask) - cz;
             if ((kb >> g.bz) != ck || dz > 2) break;
             if (dz == 2) pair((uint32_t)B, cpar[B]);
         }
-        // the 24 other columns of the 5x5 neighbourhood, kG at a time
+        // the task's groups of kG of the 24 other columns of the 5x5
+        // neighbourhood
 #pragma unroll 1
-        for (int g0 = 0; g0 < 24; g0 += kG) {
+        for (int grp = kSplit ? task : 0; grp < (kSplit ? task + 1 : (int)kGroups); ++grp) {
+            const int g0 = grp * kG;
             int dxs[kG], dys[kG];
             bool has[kG];
             uint32_t fc[kG];
@@ -2209,7 +2229,11 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     FEC_LAUNCH(kStGiant, k_giant<<<(unsigned)nframes, 1024, 0, st>>>(cpar, frames, P));
     FEC_LAUNCH(kStWorkList, k_nongiant<<<nb_cells, kBlock, 0, st>>>(cpar, gbits, work, frames,
                                                                      cell_frame, P));
-    FEC_LAUNCH(kStHookFar, k_hook_far<<<nb_cells, kBlock, 0, st>>>(
+    // both forms are launched; the one whose case the work list is not returns
+    FEC_LAUNCH(kStHookFar, k_hook_far<false><<<nb_cells, kBlock, 0, st>>>(
+                                spts, cell_start, cell_key, col_key, col_cell, colgrid, colbits,
+                                gbits, work, frames, cell_frame, cpar, P));
+    FEC_LAUNCH(kStHookFar, k_hook_far<true><<<nb_cells, kBlock, 0, st>>>(
                                 spts, cell_start, cell_key, col_key, col_cell, colgrid, colbits,
                                 gbits, work, frames, cell_frame, cpar, P));
     FEC_LAUNCH(kStCompress2, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P));
