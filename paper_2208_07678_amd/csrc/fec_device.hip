@@ -1431,6 +1431,11 @@ __constant__ StencilCol kNearCols[4] = {{0, 1}, {1, -1}, {1, 0}, {1, 1}};
 // cells within reach are located directly (column_seek) and tested after.
 constexpr int kNearK = 3;
 
+// Cell tables shorter than this give each cell two tasks, which split the
+// candidate columns between them (see k_hook_far's kFarSplitBelow).
+constexpr int64_t kNearSplitBelow = 131072;
+
+template <bool kSplit>
 __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__ spts,
                                                       const uint32_t *__restrict__ cell_start,
                                                       const uint64_t *__restrict__ cell_key,
@@ -1450,9 +1455,14 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
     constexpr int kC = 4;
     constexpr int kCand = kC * kNearK + 1;
     static_assert(kCand <= 32, "candidate masks are 32-bit");
-    for (int64_t Ai = (int64_t)blockIdx.x * kBlock + threadIdx.x; Ai < M;
-         Ai += (int64_t)gridDim.x * kBlock) {
-        const int32_t A = (int32_t)Ai;
+    if ((M < kNearSplitBelow) != kSplit) return;  // the other instance's case
+    // kSplit: two tasks per cell; task 0 takes the own column and neighbour
+    // columns 0 and 1, task 1 columns 2 and 3 (both load the cell's rounds)
+    constexpr int kTasks = kSplit ? 2 : 1;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < M * kTasks;
+         t += (int64_t)gridDim.x * kBlock) {
+        const int32_t A = (int32_t)(t / kTasks);
+        const int task = (int)(t % kTasks);
         // round 1
         const uint64_t key = cell_key[A];
         const uint64_t kup = A + 1 < M ? cell_key[A + 1] : ~0ull;
@@ -1502,6 +1512,15 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
                 if (inc && dz >= -1 && dz <= 1) cm |= 1u << (o * kNearK + j);
                 if (j == kNearK - 1 && inc && dz < 1) ovf |= 1u << o;
             }
+        }
+        if (kSplit) {
+            const uint32_t cols = task == 0 ? 0x3u : 0xCu;
+            uint32_t keep = task == 0 ? 1u << (kCand - 1) : 0u;
+#pragma unroll
+            for (int o = 0; o < kC; ++o)
+                if ((cols >> o) & 1u) keep |= ((1u << kNearK) - 1) << (o * kNearK);
+            cm &= keep;
+            ovf &= cols;
         }
         // round 4: parents and point ranges of the candidates
         int32_t rb[kCand];
@@ -2222,7 +2241,10 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     FEC_LAUNCH(kStRuns, k_runs1<<<(unsigned)ntiles, kBlock, 0, st>>>(
                             spts, cell_start, cell_key, heads, blkhead, frames, cell_frame, P));
     FEC_LAUNCH(kStRuns, k_runs2<<<(unsigned)ntiles, kBlock, 0, st>>>(heads, blkhead, cpar, P));
-    FEC_LAUNCH(kStHookNear, k_hook_near<<<nb_cells, kBlock, 0, st>>>(
+    FEC_LAUNCH(kStHookNear, k_hook_near<false><<<nb_cells, kBlock, 0, st>>>(
+                                spts, cell_start, cell_key, col_key, col_cell, colgrid, colbits,
+                                frames, cell_frame, cpar, P));
+    FEC_LAUNCH(kStHookNear, k_hook_near<true><<<nb_cells, kBlock, 0, st>>>(
                                 spts, cell_start, cell_key, col_key, col_cell, colgrid, colbits,
                                 frames, cell_frame, cpar, P));
     FEC_LAUNCH(kStCompress1, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P));
