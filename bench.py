@@ -235,7 +235,11 @@ def bench_batch(args) -> None:
     ms_per_step = timed(step, args.steps)
     dom_ms, dom_launches = fec.profile_read()[dominant]
     fec.profile_enable([])
-    avg_launch_ms = dom_ms / max(dom_launches, 1)
+    # per working launch (see the map bench: the hooking stages launch two
+    # forms of which one returns at once; sort stages once per pass)
+    dst = fec.workspace_stats(ws)
+    work_launches = (dst.get("radix_passes") or 1) if dominant.startswith("sort") else 1
+    avg_launch_ms = dom_ms / args.steps / work_launches
     bytes_per_launch = ALG_BYTES_PER_POINT.get(dominant, 16.0) * n
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
     out = {
@@ -646,25 +650,24 @@ def main():
             "hbm_GBps": None if tb is None else tb / (kernel_ms * 1e-3) / 1e9,
             "frac": None if tb is None else tb / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
-    avg_launch_ms = dom_ms / max(dom_launches, 1)
-    if dominant in ALG_BYTES_PER_POINT:
-        launches_per_step = dom_launches / args.steps
-        bytes_per_launch = ALG_BYTES_PER_POINT[dominant] * n
-        achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dominant),
-                    "kernel": dominant, "avg_launch_ms": avg_launch_ms,
-                    "launches_per_step": launches_per_step,
-                    "alg_bytes_per_launch": bytes_per_launch}
-    else:
-        # stages without a per-point byte model are reported against HBM with
-        # the bytes of their input cloud read once (a lower bound)
-        bytes_per_launch = 16.0 * n
-        achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dominant),
-                    "kernel": dominant,
-                    "avg_launch_ms": avg_launch_ms, "alg_bytes_per_launch": bytes_per_launch}
+    # The stage's time per call covers all its launches: the sort stages run
+    # once per radix pass (passes beyond the key's width return at once), the
+    # two hooking stages launch a large-cloud and a small-cloud form of which
+    # one returns at once.  Per working launch: the stage time per call over
+    # the working launches.
+    passes = stats.get("radix_passes") or 0
+    work_launches = passes if dominant.startswith("sort") else 1
+    avg_launch_ms = dom_ms / args.steps / max(work_launches, 1)
+    # stages without a per-point byte model are reported against HBM with the
+    # bytes of their cells' points read once (a lower bound)
+    bytes_per_launch = ALG_BYTES_PER_POINT.get(dominant, 16.0) * n
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dominant),
+                "kernel": dominant, "avg_launch_ms": avg_launch_ms,
+                "launches_per_step": dom_launches / args.steps,
+                "working_launches_per_step": work_launches,
+                "alg_bytes_per_launch": bytes_per_launch}
 
     cpu = None
     if args.cpu_frames > 0 and args.workload == "map27m":
