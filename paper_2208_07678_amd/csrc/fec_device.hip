@@ -154,15 +154,29 @@ __global__ __launch_bounds__(kBlock) void k_bbox(const float *__restrict__ xyz, 
     float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY;
     float hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
     uint32_t cnt = 0;
-    for (int64_t i = lo + (int64_t)j * kBlock + threadIdx.x; i < hi;
-         i += (int64_t)per_frame * kBlock) {
-        const float x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+    auto take = [&](float x, float y, float z) {
         if (finite3(x, y, z)) {
             lo0 = fminf(lo0, x); lo1 = fminf(lo1, y); lo2 = fminf(lo2, z);
             hi0 = fmaxf(hi0, x); hi1 = fmaxf(hi1, y); hi2 = fmaxf(hi2, z);
             ++cnt;
         }
+    };
+    const int64_t stride = (int64_t)per_frame * kBlock;
+    int64_t i = lo + (int64_t)j * kBlock + threadIdx.x;
+    constexpr int kU = 4;  // points per lane whose loads are in flight together
+    for (; i + (kU - 1) * stride < hi; i += kU * stride) {
+        float x[kU], y[kU], z[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int64_t q = i + u * stride;
+            x[u] = xyz[3 * q];
+            y[u] = xyz[3 * q + 1];
+            z[u] = xyz[3 * q + 2];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) take(x[u], y[u], z[u]);
     }
+    for (; i < hi; i += stride) take(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         lo0 = fminf(lo0, __shfl_xor(lo0, o)); lo1 = fminf(lo1, __shfl_xor(lo1, o));
@@ -1969,13 +1983,9 @@ __global__ __launch_bounds__(kBlock) void k_final_cells(const int32_t *__restric
             r = cpar[A];
             const uint32_t s = cell_start[A], e = cell_start[A + 1];
             cnt = e - s;
-            for (uint32_t p = s; p < e; p += 4) {  // four loads in flight
-                uint32_t o[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) o[j] = sorig[p + j < e ? p + j : e - 1];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) mn = o[j] < mn ? o[j] : mn;
-            }
+            // the radix sort is stable and its input is in index order, so
+            // a cell's words keep index order: its first is its smallest
+            mn = sorig[s];
             cmax = cnt > cmax ? cnt : cmax;
         }
         const uint64_t act = __ballot(valid);
@@ -2001,6 +2011,25 @@ __global__ __launch_bounds__(kBlock) void k_final_cells(const int32_t *__restric
         }
     }
     if (threadIdx.x == 0) atomicMax(&P->max_cell, (int32_t)s_max);
+}
+
+// Every label -1, in one coalesced pass: the label kernel then writes only
+// the points of kept clusters.  Their writes land in scattered places of the
+// caller's array (the sorted order is unrelated to the input's), where each
+// costs a partial line, so on clouds whose points mostly end in filtered
+// clusters the pass saves most of the label traffic.
+__global__ __launch_bounds__(kBlock) void k_labels_clear(int32_t *__restrict__ labels, int64_t n,
+                                                         const Params *__restrict__ P) {
+    if (P->status != kStatusOk) return;
+    int4 *l4 = reinterpret_cast<int4 *>(labels);
+    const int64_t n4 = ((uintptr_t)labels & 15) == 0 ? n / 4 : 0;
+    const int4 m1 = make_int4(-1, -1, -1, -1);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n4;
+         i += (int64_t)gridDim.x * kBlock)
+        l4[i] = m1;
+    for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        labels[i] = -1;
 }
 
 // Labels in the caller's order and the number of kept clusters.  With
@@ -2052,6 +2081,7 @@ __global__ __launch_bounds__(kBlock) void k_final_labels(const int32_t *__restri
                 }
             }
         }
+        if (!ok) continue;  // -1 is there already (k_labels_clear)
         const uint32_t s = cell_start[A], e = cell_start[A + 1];
         for (uint32_t p = s; p < e; p += 4) {  // four loads in flight
             uint32_t o[4];
@@ -2080,7 +2110,7 @@ __global__ __launch_bounds__(kBlock) void k_final_labels(const int32_t *__restri
             accepted = frames[f].status == kStatusOk;
         }
         const bool one_ok = accepted && lo <= 1u && 1u <= hi;
-        labels[o] = one_ok ? (int32_t)o - base : -1;
+        if (one_ok) labels[o] = (int32_t)o - base;
         if (!batched) kept += one_ok ? 1u : 0u;
         else if (one_ok) atomicAdd(&frames[f].kept, 1);
     }
@@ -2261,6 +2291,7 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     FEC_LAUNCH(kStCompress2, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P));
     FEC_LAUNCH(kStFinalCells, k_final_cells<<<nb_cells, kBlock, 0, st>>>(
                                   cpar, cell_start, sorig, csize, ccanon, P));
+    FEC_LAUNCH(kStFinalLabels, k_labels_clear<<<nb_stream, kBlock, 0, st>>>(labels_out, n, P));
     FEC_LAUNCH(kStFinalLabels, k_final_labels<<<nb_cells, kBlock, 0, st>>>(
                                    cpar, cell_start, sorig, csize, ccanon, labels_out, frames,
                                    cell_frame, P));
