@@ -551,12 +551,14 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(const uint64_t *__restrict
         const int64_t e = base + k * 64 + lane;
         v[k] = e < n ? src[e] : 0ull;
     }
+    // counts only (no ranks): one LDS atomic add per word, into the wave's
+    // own row; lanes adding to one counter are serialised by the LDS, which
+    // still costs far less than the eight ballots of a stable rank
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const bool valid = base + k * 64 + lane < n;
         const uint32_t dg = (uint32_t)(v[k] >> shift) & (kRadix - 1);
-        const uint64_t peers = digit_peers(dg, valid);
-        if (valid && (peers & lanemask_lt()) == 0) s_cnt[wave][dg] += (uint32_t)__popcll(peers);
+        if (valid) atomicAdd(&s_cnt[wave][dg], 1u);
     }
     __syncthreads();
     uint32_t c = 0;
