@@ -1150,6 +1150,30 @@ __device__ __forceinline__ void find_columns(const Grid &g, const ColIndex &ci,
 }
 
 // ------------------------------------------------------------- 8. hooking
+// Blocks go to the 8 XCDs round-robin by block id, and each XCD has its own
+// L2.  xcd_block<C>() renumbers the blocks so that each XCD runs runs of C
+// consecutive block numbers: in every group of 8C blocks, XCD x takes
+// numbers x*C .. x*C+C-1.  With C blocks of cells spanning a cell's
+// neighbours in the next x slab (a few hundred cells further), those
+// neighbours are loaded by the same XCD at about the same time; groups keep
+// rotating over the XCDs, so the load stays spread when the work per cell
+// varies along the cells.  A bijection on [0, gridDim.x) when the grid is a
+// multiple of 8C (the identity otherwise; C = 1 is the identity).
+constexpr uint32_t kXcds = 8;
+template <uint32_t C>
+__device__ __forceinline__ int64_t xcd_block() {
+    const uint32_t g = gridDim.x, b = blockIdx.x, span = kXcds * C;
+    if (C == 1 || g % span) return b;
+    const uint32_t r = b % span;
+    return (int64_t)(b - r) + (r % kXcds) * C + r / kXcds;
+}
+// Run lengths C of the two hooking kernels, measured on the 27 M map (near shell 2.34 -> 2.10 ms, far
+// shell 1.04 -> 0.98 ms) with batches of frames unchanged.  The far shell's
+// work list is sparse in the cells and gains less; whole eighths per XCD
+// (C = gridDim.x / 8) unbalance both shells on batches (near 0.44 -> 0.64 ms).
+constexpr uint32_t kXcdRunNear = 64;
+constexpr uint32_t kXcdRunFar = 16;
+
 // Union-find over cells.  Two roots are joined by hooking the one of higher
 // rank under the other, rank being a fixed bijective scramble of the cell
 // id: a strict total order keeps the forest acyclic under concurrent hooks,
@@ -1475,7 +1499,7 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
     // kSplit: two tasks per cell; task 0 takes the own column and neighbour
     // columns 0 and 1, task 1 columns 2 and 3 (both load the cell's rounds)
     constexpr int kTasks = kSplit ? 2 : 1;
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < M * kTasks;
+    for (int64_t t = xcd_block<kXcdRunNear>() * kBlock + threadIdx.x; t < M * kTasks;
          t += (int64_t)gridDim.x * kBlock) {
         const int32_t A = (int32_t)(t / kTasks);
         const int task = (int)(t % kTasks);
@@ -1805,7 +1829,7 @@ __global__ __launch_bounds__(kBlock) void k_hook_far(const float4 *__restrict__ 
     constexpr uint32_t kGroups = 24 / kG;
     constexpr uint32_t kTasks = kSplit ? kGroups : 1;
     const uint64_t ntask = (uint64_t)nwork * kTasks;
-    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < ntask;
+    for (uint64_t t = (uint64_t)xcd_block<kXcdRunFar>() * kBlock + threadIdx.x; t < ntask;
          t += (uint64_t)gridDim.x * kBlock) {
         const uint32_t wi = (uint32_t)(t / kTasks);
         const int task = (int)(t % kTasks);
