@@ -1451,7 +1451,12 @@ __device__ __forceinline__ uint32_t column_seek(const uint64_t *__restrict__ cel
 
 // Forward half of the 5x5x5 stencil by column offset (dx, dy): the near
 // shell (max(|dx|,|dy|,|dz|) == 1) uses the first four columns with
-// |dz| <= 1; the own column contributes dz = +1.
+// |dz| <= 1.  The own column's dz = +1 needs no test there: the runs pass
+// has tested every cell against the next cell when that one is its own
+// column's dz = +1 or column (0, +1) within dz +- 1 (next_is_near), and
+// joined such pairs share a run; unjoined ones have no edge.  For the same
+// reason the near shell skips column (0, +1)'s first cell when it is the
+// very next cell.
 struct StencilCol {
     int8_t dx, dy;
 };
@@ -1493,11 +1498,11 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
     const bool batched = P->nframes > 1;
     const Grid g = grid_of(P);
     constexpr int kC = 4;
-    constexpr int kCand = kC * kNearK + 1;
+    constexpr int kCand = kC * kNearK;
     static_assert(kCand <= 32, "candidate masks are 32-bit");
     if ((M < kNearSplitBelow) != kSplit) return;  // the other instance's case
-    // kSplit: two tasks per cell; task 0 takes the own column and neighbour
-    // columns 0 and 1, task 1 columns 2 and 3 (both load the cell's rounds)
+    // kSplit: two tasks per cell; task 0 takes neighbour columns 0 and 1,
+    // task 1 columns 2 and 3 (both load the cell's rounds)
     constexpr int kTasks = kSplit ? 2 : 1;
     for (int64_t t = xcd_block<kXcdRunNear>() * kBlock + threadIdx.x; t < M * kTasks;
          t += (int64_t)gridDim.x * kBlock) {
@@ -1505,7 +1510,6 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
         const int task = (int)(t % kTasks);
         // round 1
         const uint64_t key = cell_key[A];
-        const uint64_t kup = A + 1 < M ? cell_key[A + 1] : ~0ull;
         const uint32_t sA = cell_start[A], eA = cell_start[A + 1];
         const int32_t p0 = cpar[A];
         const uint32_t fA = batched ? cell_frame[A] : 0u;
@@ -1540,8 +1544,6 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
         // candidates (existence is tracked explicitly: a key sentinel could
         // equal the wrapped key of a column off the grid)
         uint32_t cm = 0, ovf = 0;
-        if (A + 1 < M && (kup >> g.bz) == ck && (int64_t)(kup & g.zmask) == cz + 1)
-            cm |= 1u << (kCand - 1);
 #pragma unroll
         for (int o = 0; o < kC; ++o) {
 #pragma unroll
@@ -1553,9 +1555,12 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
                 if (j == kNearK - 1 && inc && dz < 1) ovf |= 1u << o;
             }
         }
+        // column 0 is (0, +1): its first cell, when it is the next cell, was
+        // decided by the runs pass
+        if (fc[0] == (uint32_t)A + 1) cm &= ~1u;
         if (kSplit) {
             const uint32_t cols = task == 0 ? 0x3u : 0xCu;
-            uint32_t keep = task == 0 ? 1u << (kCand - 1) : 0u;
+            uint32_t keep = 0;
 #pragma unroll
             for (int o = 0; o < kC; ++o)
                 if ((cols >> o) & 1u) keep |= ((1u << kNearK) - 1) << (o * kNearK);
@@ -1567,7 +1572,7 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
         uint32_t sb[kCand], eb[kCand];
 #pragma unroll
         for (int i = 0; i < kCand; ++i) {
-            const uint32_t B = i == kCand - 1 ? (uint32_t)A + 1 : fc[i / kNearK] + (uint32_t)(i % kNearK);
+            const uint32_t B = fc[i / kNearK] + (uint32_t)(i % kNearK);
             const bool c = (cm >> i) & 1u;
             rb[i] = c ? cpar[B] : -1;
             sb[i] = c ? cell_start[B] : 0u;
