@@ -1474,7 +1474,14 @@ __constant__ StencilCol kNearCols[4] = {{0, 1}, {1, -1}, {1, 0}, {1, 1}};
 // candidates whose component differs tested one by one.  When the cells
 // loaded from a column stop below A's reach (a tall column), the column's
 // cells within reach are located directly (column_seek) and tested after.
-constexpr int kNearK = 3;
+//
+// One cell per column (kNearK = 1) is fastest on the map and on batches of
+// frames, although more columns then take the second path: the kernel's
+// registers (94 against 115 with two cells and 139 with three) allow five
+// waves per SIMD instead of four or three, and the columns of these clouds
+// hold 1.5 cells on average, so most of the further loads were wasted.
+// Measured per call: map 2.08 -> 1.71 ms, 64-frame batch 0.45 -> 0.32 ms.
+constexpr int kNearK = 1;
 
 // Cell tables shorter than this give each cell two tasks, which split the
 // candidate columns between them (see k_hook_far's kFarSplitBelow).
