@@ -1830,8 +1830,15 @@ __global__ __launch_bounds__(kBlock) void k_hook_far(const float4 *__restrict__ 
     const float d2_one = P->d2;
     const bool batched = P->nframes > 1;
     const Grid g = grid_of(P);
-    constexpr int kG = 8;      // columns per group (loads issued together)
-    constexpr int kK = 2;      // cells per column loaded up front
+    // Columns per group (their loads issued together) and cells per column
+    // loaded up front.  Small groups and one cell keep the registers low
+    // (88 with groups of 3, 65 with single columns, against 163 with groups
+    // of 8 and two cells), so more waves hide the loads' latency; measured
+    // per call with groups of 3: map 0.97 -> 0.70 ms, 64-frame batch 0.51
+    // -> 0.39 ms.  Small work lists (kSplit) give each column a task of its
+    // own: 120 k frame 0.058 -> 0.046 ms.
+    constexpr int kG = kSplit ? 1 : 3;
+    constexpr int kK = 1;
     static_assert(kG * kK <= 32, "candidate masks are 32-bit");
     static_assert(kG <= 32 && 24 % kG == 0, "groups cover the 24 columns");
     if ((nwork < kFarSplitBelow) != kSplit) return;  // the other instance's case
