@@ -1457,10 +1457,11 @@ __device__ __forceinline__ uint32_t column_seek(const uint64_t *__restrict__ cel
 // joined such pairs share a run; unjoined ones have no edge.  For the same
 // reason the near shell skips column (0, +1)'s first cell when it is the
 // very next cell.
-struct StencilCol {
-    int8_t dx, dy;
-};
-__constant__ StencilCol kNearCols[4] = {{0, 1}, {1, -1}, {1, 0}, {1, 1}};
+// Near-shell column q (0..3): (0, +1), (1, -1), (1, 0), (1, +1).
+__device__ __forceinline__ void near_col(int q, int &dx, int &dy) {
+    dx = q == 0 ? 0 : 1;
+    dy = q == 0 ? 1 : q - 2;
+}
 
 // Near shell over every cell: a cell pair is skipped when both cells
 // already share a root; otherwise point pairs are tested until the first
@@ -1468,9 +1469,10 @@ __constant__ StencilCol kNearCols[4] = {{0, 1}, {1, -1}, {1, 0}, {1, 1}};
 //
 // The kernel is latency bound, so the loads of one cell are issued in a
 // few independent rounds rather than as one long dependent chain: (1) the
-// cell's own key, points and parent; (2) occupancy bit and index entry of
-// the four neighbour columns; (3) the first kNearK cells of each of those
-// columns; (4) the parents of every candidate cell.  Only then are the
+// cell's own key, points, parent and the parent's parent; (2) occupancy bit
+// and index entry of a group of neighbour columns (all four on large cell
+// tables, two per task on small ones); (3) the first kNearK cells of each of
+// those columns; (4) the parents of every candidate cell.  Only then are the
 // candidates whose component differs tested one by one.  When the cells
 // loaded from a column stop below A's reach (a tall column), the column's
 // cells within reach are located directly (column_seek) and tested after.
@@ -1482,6 +1484,9 @@ __constant__ StencilCol kNearCols[4] = {{0, 1}, {1, -1}, {1, 0}, {1, 1}};
 // hold 1.5 cells on average, so most of the further loads were wasted.
 // Measured per call: map 2.08 -> 1.71 ms, 64-frame batch 0.45 -> 0.32 ms.
 constexpr int kNearK = 1;
+// Columns per group on large cell tables: all four (groups of two or one,
+// with fewer registers, measured slower on the map: 1.67 -> 1.76 / 1.97 ms).
+constexpr int kNearGroup = 4;
 
 // Cell tables shorter than this give each cell two tasks, which split the
 // candidate columns between them (see k_hook_far's kFarSplitBelow).
@@ -1505,12 +1510,15 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
     const bool batched = P->nframes > 1;
     const Grid g = grid_of(P);
     constexpr int kC = 4;
-    constexpr int kCand = kC * kNearK;
-    static_assert(kCand <= 32, "candidate masks are 32-bit");
+    // columns per group: a group's loads are issued together, the groups of
+    // a cell one after the other (fewer registers, more waves)
+    constexpr int kNG = kSplit ? 2 : kNearGroup;
+    constexpr int kGroups = kC / kNG;
+    constexpr int kCand = kNG * kNearK;
+    static_assert(kC % kNG == 0 && kCand <= 32, "groups cover the columns; 32-bit masks");
     if ((M < kNearSplitBelow) != kSplit) return;  // the other instance's case
-    // kSplit: two tasks per cell; task 0 takes neighbour columns 0 and 1,
-    // task 1 columns 2 and 3 (both load the cell's rounds)
-    constexpr int kTasks = kSplit ? 2 : 1;
+    // kSplit: one task per (cell, group); both tasks load the cell's own data
+    constexpr int kTasks = kSplit ? kGroups : 1;
     for (int64_t t = xcd_block<kXcdRunNear>() * kBlock + threadIdx.x; t < M * kTasks;
          t += (int64_t)gridDim.x * kBlock) {
         const int32_t A = (int32_t)(t / kTasks);
@@ -1525,117 +1533,117 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
         int64_t cx, cy;
         g.col_xy(ck, cx, cy);
         const float4 pa = spts[sA];  // A's first point, for the one-pair tests
-        // round 2: neighbour columns
-        bool has[kC];
-        uint32_t fc[kC];
-        uint64_t want[kC];
-        int64_t nxs[kC], nys[kC];
-#pragma unroll
-        for (int o = 0; o < kC; ++o) {
-            const StencilCol sc = kNearCols[o];
-            nxs[o] = cx + sc.dx;
-            nys[o] = cy + sc.dy;
-            want[o] = g.col_key((uint64_t)nxs[o], (uint64_t)nys[o]);
-        }
-        find_columns<kC>(g, ci, nxs, nys, has, fc);
-        // round 3: first cells of each column
-        uint64_t kk[kC][kNearK];
-#pragma unroll
-        for (int o = 0; o < kC; ++o)
-#pragma unroll
-            for (int j = 0; j < kNearK; ++j) {
-                const int64_t B = (int64_t)fc[o] + j;
-                kk[o][j] = (has[o] && B < M) ? cell_key[B] : ~0ull;
-            }
         const int32_t q0 = cpar[p0];
-        // candidates (existence is tracked explicitly: a key sentinel could
-        // equal the wrapped key of a column off the grid)
-        uint32_t cm = 0, ovf = 0;
-#pragma unroll
-        for (int o = 0; o < kC; ++o) {
-#pragma unroll
-            for (int j = 0; j < kNearK; ++j) {
-                const bool loaded = has[o] && (int64_t)fc[o] + j < M;
-                const bool inc = loaded && (kk[o][j] >> g.bz) == want[o];
-                const int64_t dz = (int64_t)(kk[o][j] & g.zmask) - cz;
-                if (inc && dz >= -1 && dz <= 1) cm |= 1u << (o * kNearK + j);
-                if (j == kNearK - 1 && inc && dz < 1) ovf |= 1u << o;
-            }
-        }
-        // column 0 is (0, +1): its first cell, when it is the next cell, was
-        // decided by the runs pass
-        if (fc[0] == (uint32_t)A + 1) cm &= ~1u;
-        if (kSplit) {
-            const uint32_t cols = task == 0 ? 0x3u : 0xCu;
-            uint32_t keep = 0;
-#pragma unroll
-            for (int o = 0; o < kC; ++o)
-                if ((cols >> o) & 1u) keep |= ((1u << kNearK) - 1) << (o * kNearK);
-            cm &= keep;
-            ovf &= cols;
-        }
-        // round 4: parents and point ranges of the candidates
-        int32_t rb[kCand];
-        uint32_t sb[kCand], eb[kCand];
-#pragma unroll
-        for (int i = 0; i < kCand; ++i) {
-            const uint32_t B = fc[i / kNearK] + (uint32_t)(i % kNearK);
-            const bool c = (cm >> i) & 1u;
-            rb[i] = c ? cpar[B] : -1;
-            sb[i] = c ? cell_start[B] : 0u;
-            eb[i] = c ? cell_start[B + 1] : 0u;
-        }
-        int32_t ra = (q0 == p0) ? p0 : uf_find(cpar, q0);
         const float d2 = batched ? frames[fA].d2 : d2_one;  // neighbours share A's frame
-        FEC_COUNT(P, 0, __popc(cm));
-        // round 5: the first point of every candidate in another component,
-        // tested against A's first point all at once; that one pair decides
-        // most joined cell pairs, the others are scanned in full below
-        uint32_t need = 0, quick = 0;
+        int32_t ra = -1;  // A's root, found once the first group's loads are out
+#pragma unroll 1
+        for (int grp = kSplit ? task : 0; grp < (kSplit ? task + 1 : kGroups); ++grp) {
+            const int o0 = grp * kNG;
+            // round 2: neighbour columns
+            bool has[kNG];
+            uint32_t fc[kNG];
+            uint64_t want[kNG];
+            int64_t nxs[kNG], nys[kNG];
 #pragma unroll
-        for (int i = 0; i < kCand; ++i) {
-            const bool nd = ((cm >> i) & 1u) && rb[i] != ra && rb[i] != p0;
-            need |= (uint32_t)nd << i;
-            if (nd) quick |= (uint32_t)joined(pa.x, pa.y, pa.z, spts[sb[i]], d2) << i;
-        }
-#pragma unroll
-        for (int i = 0; i < kCand; ++i) {
-            if (!((need >> i) & 1u)) continue;
-            const int32_t r = uf_find(cpar, rb[i]);
-            if (r == ra) continue;
-            FEC_COUNT(P, 1, 1);
-            FEC_COUNT(P, 3, (eA - sA) * (eb[i] - sb[i]));
-            if (((quick >> i) & 1u) || any_joined(spts, sA, eA, sb[i], eb[i], d2)) {
-                FEC_COUNT(P, 2, 1);
-                ra = uf_link_roots(cpar, uf_find(cpar, ra), r);
+            for (int o = 0; o < kNG; ++o) {
+                int dx, dy;
+                near_col(o0 + o, dx, dy);
+                nxs[o] = cx + dx;
+                nys[o] = cy + dy;
+                want[o] = g.col_key((uint64_t)nxs[o], (uint64_t)nys[o]);
             }
-        }
-        FEC_COUNT(P, 4, __popc(ovf));
-        // columns with cells in reach beyond the loaded ones: at most three
-        // more (z within cz +- 1, distinct), from the first one not below
-        if (ovf) {
-            for (int o = 0; o < kC; ++o) {
-                if (!((ovf >> o) & 1u)) continue;
-                const int64_t zl = (int64_t)(kk[o][kNearK - 1] & g.zmask);
-                const uint32_t st =
-                    zl >= cz - 1 ? fc[o] + kNearK
-                                 : column_seek(cell_key, M, g.bz, want[o], fc[o],
-                                               (int64_t)(kk[o][0] & g.zmask), fc[o] + kNearK,
-                                               cz - 1);
-                uint64_t kx[3];
+            find_columns<kNG>(g, ci, nxs, nys, has, fc);
+            // round 3: first cells of each column
+            uint64_t kk[kNG][kNearK];
 #pragma unroll
-                for (int j = 0; j < 3; ++j) kx[j] = (int64_t)st + j < M ? cell_key[st + j] : ~0ull;
+            for (int o = 0; o < kNG; ++o)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    const uint32_t B = st + j;
-                    if ((int64_t)B >= M || (kx[j] >> g.bz) != want[o]) break;
-                    const int64_t dz = (int64_t)(kx[j] & g.zmask) - cz;
-                    if (dz > 1) break;
-                    if (dz < -1) continue;
-                    const int32_t r = uf_find(cpar, (int32_t)B);
-                    if (r == ra) continue;
-                    if (any_joined(spts, sA, eA, cell_start[B], cell_start[B + 1], d2))
-                        ra = uf_link(cpar, ra, r);
+                for (int j = 0; j < kNearK; ++j) {
+                    const int64_t B = (int64_t)fc[o] + j;
+                    kk[o][j] = (has[o] && B < M) ? cell_key[B] : ~0ull;
+                }
+            // candidates (existence is tracked explicitly: a key sentinel
+            // could equal the wrapped key of a column off the grid)
+            uint32_t cm = 0, ovf = 0;
+#pragma unroll
+            for (int o = 0; o < kNG; ++o) {
+#pragma unroll
+                for (int j = 0; j < kNearK; ++j) {
+                    const bool loaded = has[o] && (int64_t)fc[o] + j < M;
+                    const bool inc = loaded && (kk[o][j] >> g.bz) == want[o];
+                    const int64_t dz = (int64_t)(kk[o][j] & g.zmask) - cz;
+                    if (inc && dz >= -1 && dz <= 1) cm |= 1u << (o * kNearK + j);
+                    if (j == kNearK - 1 && inc && dz < 1) ovf |= 1u << o;
+                }
+            }
+            // column 0 is (0, +1): its first cell, when it is the next cell,
+            // was decided by the runs pass
+            if (o0 == 0 && fc[0] == (uint32_t)A + 1) cm &= ~1u;
+            // round 4: parents and point ranges of the candidates
+            int32_t rb[kCand];
+            uint32_t sb[kCand], eb[kCand];
+#pragma unroll
+            for (int i = 0; i < kCand; ++i) {
+                const uint32_t B = fc[i / kNearK] + (uint32_t)(i % kNearK);
+                const bool c = (cm >> i) & 1u;
+                rb[i] = c ? cpar[B] : -1;
+                sb[i] = c ? cell_start[B] : 0u;
+                eb[i] = c ? cell_start[B + 1] : 0u;
+            }
+            if (ra < 0) ra = (q0 == p0) ? p0 : uf_find(cpar, q0);
+            FEC_COUNT(P, 0, __popc(cm));
+            // round 5: the first point of every candidate in another
+            // component, tested against A's first point all at once; that
+            // one pair decides most joined cell pairs, the others are
+            // scanned in full below
+            uint32_t need = 0, quick = 0;
+#pragma unroll
+            for (int i = 0; i < kCand; ++i) {
+                const bool nd = ((cm >> i) & 1u) && rb[i] != ra && rb[i] != p0;
+                need |= (uint32_t)nd << i;
+                if (nd) quick |= (uint32_t)joined(pa.x, pa.y, pa.z, spts[sb[i]], d2) << i;
+            }
+#pragma unroll
+            for (int i = 0; i < kCand; ++i) {
+                if (!((need >> i) & 1u)) continue;
+                const int32_t r = uf_find(cpar, rb[i]);
+                if (r == ra) continue;
+                FEC_COUNT(P, 1, 1);
+                FEC_COUNT(P, 3, (eA - sA) * (eb[i] - sb[i]));
+                if (((quick >> i) & 1u) || any_joined(spts, sA, eA, sb[i], eb[i], d2)) {
+                    FEC_COUNT(P, 2, 1);
+                    ra = uf_link_roots(cpar, uf_find(cpar, ra), r);
+                }
+            }
+            FEC_COUNT(P, 4, __popc(ovf));
+            // columns with cells in reach beyond the loaded ones: at most
+            // three more (z within cz +- 1, distinct), from the first one
+            // not below
+            if (ovf) {
+                for (int o = 0; o < kNG; ++o) {
+                    if (!((ovf >> o) & 1u)) continue;
+                    const int64_t zl = (int64_t)(kk[o][kNearK - 1] & g.zmask);
+                    const uint32_t st =
+                        zl >= cz - 1 ? fc[o] + kNearK
+                                     : column_seek(cell_key, M, g.bz, want[o], fc[o],
+                                                   (int64_t)(kk[o][0] & g.zmask),
+                                                   fc[o] + kNearK, cz - 1);
+                    uint64_t kx[3];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+                        kx[j] = (int64_t)st + j < M ? cell_key[st + j] : ~0ull;
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const uint32_t B = st + j;
+                        if ((int64_t)B >= M || (kx[j] >> g.bz) != want[o]) break;
+                        const int64_t dz = (int64_t)(kx[j] & g.zmask) - cz;
+                        if (dz > 1) break;
+                        if (dz < -1) continue;
+                        const int32_t r = uf_find(cpar, (int32_t)B);
+                        if (r == ra) continue;
+                        if (any_joined(spts, sA, eA, cell_start[B], cell_start[B + 1], d2))
+                            ra = uf_link(cpar, ra, r);
+                    }
                 }
             }
         }
