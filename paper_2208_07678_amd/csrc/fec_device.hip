@@ -607,7 +607,10 @@ __global__ __launch_bounds__(kBlock) void k_sort_scan(Params *__restrict__ P, in
 }
 
 // (3) stable scatter of one tile.
-__global__ __launch_bounds__(kBlock) void k_sort_scatter(const uint64_t *__restrict__ src,
+// Four waves per SIMD: its LDS allows four blocks per CU, and 129 registers
+// would allow three (one 8-byte spill at 128; scatter 0.59 -> 0.55 ms per map
+// call).
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_sort_scatter(const uint64_t *__restrict__ src,
                                                          uint64_t *__restrict__ dst,
                                                          const uint32_t *__restrict__ srcv,
                                                          uint32_t *__restrict__ dstv,
@@ -1471,11 +1474,12 @@ __device__ __forceinline__ void near_col(int q, int &dx, int &dy) {
 // few independent rounds rather than as one long dependent chain: (1) the
 // cell's own key, points, parent and the parent's parent; (2) occupancy bit
 // and index entry of a group of neighbour columns (all four on large cell
-// tables, two per task on small ones); (3) the first kNearK cells of each of
-// those columns; (4) the parents of every candidate cell.  Only then are the
-// candidates whose component differs tested one by one.  When the cells
-// loaded from a column stop below A's reach (a tall column), the column's
-// cells within reach are located directly (column_seek) and tested after.
+// tables; on small ones one column per task); (3) the first kNearK cells
+// of each of those columns; (4) the parents of every candidate cell.  Only
+// then are the candidates whose component differs tested one by one.  When
+// the cells loaded from a column stop below A's reach (a tall column), the
+// column's cells within reach are located directly (column_seek) and tested
+// after.
 //
 // One cell per column (kNearK = 1) is fastest on the map and on batches of
 // frames, although more columns then take the second path: the kernel's
@@ -1488,8 +1492,8 @@ constexpr int kNearK = 1;
 // with fewer registers, measured slower on the map: 1.67 -> 1.76 / 1.97 ms).
 constexpr int kNearGroup = 4;
 
-// Cell tables shorter than this give each cell two tasks, which split the
-// candidate columns between them (see k_hook_far's kFarSplitBelow).
+// Cell tables shorter than this give each cell four tasks, one per
+// candidate column (see k_hook_far's kFarSplitBelow).
 constexpr int64_t kNearSplitBelow = 131072;
 
 template <bool kSplit>
@@ -1512,12 +1516,12 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
     constexpr int kC = 4;
     // columns per group: a group's loads are issued together, the groups of
     // a cell one after the other (fewer registers, more waves)
-    constexpr int kNG = kSplit ? 2 : kNearGroup;
+    constexpr int kNG = kSplit ? 1 : kNearGroup;
     constexpr int kGroups = kC / kNG;
     constexpr int kCand = kNG * kNearK;
     static_assert(kC % kNG == 0 && kCand <= 32, "groups cover the columns; 32-bit masks");
     if ((M < kNearSplitBelow) != kSplit) return;  // the other instance's case
-    // kSplit: one task per (cell, group); both tasks load the cell's own data
+    // kSplit: one task per (cell, group); every task loads the cell's own data
     constexpr int kTasks = kSplit ? kGroups : 1;
     for (int64_t t = xcd_block<kXcdRunNear>() * kBlock + threadIdx.x; t < M * kTasks;
          t += (int64_t)gridDim.x * kBlock) {
