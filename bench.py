@@ -36,7 +36,7 @@ ALG_BYTES_PER_POINT = {
     "sort_hist": 8.0,     # read one 8-byte packed key per pass
     "sort_scatter": 16.0,  # read + write one 8-byte packed key per pass
     "gather": 8.0 + 12.0 + 16.0 + 4.0,  # read key, read xyz, write float4 + index
-    "final_labels": 4.0 + 4.0,  # read original index, write label
+    "final_labels": 4.0,  # write every label once (-1 pass); kept clusters' labels again
 }
 
 
