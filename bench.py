@@ -111,28 +111,33 @@ def _source_digest() -> str:
     return h.hexdigest()
 
 
-def _traffic_record():
-    path = os.path.join(ROOT, "profiles", "traffic_map27m.json")
+def _traffic_record(workload: str):
+    """The committed counter summary of `workload`, while the kernel sources
+    are the ones it was taken with; None otherwise (counters are per
+    workload: one cloud's bytes say nothing of another's)."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
     try:
         with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    return rec if rec.get("source_sha256") == _source_digest() else None
+    if rec.get("workload") != workload or rec.get("source_sha256") != _source_digest():
+        return None
+    return rec
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None when there is none for it or the kernel sources changed since."""
-    rec = _traffic_record()
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    counter summary, or None (see _traffic_record)."""
+    rec = _traffic_record(workload)
     k = None if rec is None else rec.get("kernels", {}).get(kernel)
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-def path_traffic(passes: int):
-    """Measured HBM bytes of one whole call on the map (every kernel, the
-    sort's kernels once per pass), or None (see measured_traffic)."""
-    rec = _traffic_record()
+def path_traffic(workload: str, passes: int):
+    """Measured HBM bytes of one whole call on `workload` (every kernel, the
+    sort's kernels once per pass), or None (see _traffic_record)."""
+    rec = _traffic_record(workload)
     if rec is None:
         return None
     tot = 0
@@ -645,7 +650,7 @@ def main():
     call_ms = {"median": float(np.median(per_call)), "p99": float(np.percentile(per_call, 99)),
                "blocking_median": float(np.median(blocking))}
     kernel_ms = sum(v[0] for v in prof_all.values())
-    tb = path_traffic(stats.get("radix_passes") or 0)
+    tb = path_traffic(args.workload, stats.get("radix_passes") or 0)
     path = {"kernel_ms": kernel_ms, "hbm_bytes": tb,
             "hbm_GBps": None if tb is None else tb / (kernel_ms * 1e-3) / 1e9,
             "frac": None if tb is None else tb / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
@@ -663,7 +668,7 @@ def main():
     bytes_per_launch = ALG_BYTES_PER_POINT.get(dominant, 16.0) * n
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dominant),
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, dominant),
                 "kernel": dominant, "avg_launch_ms": avg_launch_ms,
                 "launches_per_step": dom_launches / args.steps,
                 "working_launches_per_step": work_launches,
