@@ -1350,20 +1350,50 @@ __global__ __launch_bounds__(kBlock) void k_runs1(const float4 *__restrict__ spt
     const bool batched = P->nframes > 1;
     const Grid g = grid_of(P);
     int32_t last = -1;
-    for (int k = 0; k < kItems; ++k) {
-        const int64_t A = base + k * kBlock + threadIdx.x;
-        if (A >= M) break;
-        bool head = true;
-        if (A > 0) {
-            const uint64_t kp = cell_key[A - 1], ka = cell_key[A];
-            if (next_is_near(g, kp, ka)) {  // same x, so the same frame
-                const float d2 = batched ? frames[cell_frame[A]].d2 : d2_one;
-                head = !any_joined_1(spts, cell_start[A - 1], cell_start[A], cell_start[A],
-                                     cell_start[A + 1], d2);
-            }
+    // kR cells per lane at a time, their loads issued in rounds (keys; cell
+    // starts and thresholds; the first point of both cells), so that a lane
+    // does not wait on one chain of dependent loads per cell in turn
+    constexpr int kR = 4;
+    static_assert(kItems % kR == 0, "rounds cover the tile");
+    for (int k0 = 0; k0 < kItems; k0 += kR) {
+        int64_t A[kR];
+        bool in[kR], nr[kR];
+        uint64_t kp[kR], ka[kR];
+        uint32_t fr[kR];
+#pragma unroll
+        for (int u = 0; u < kR; ++u) {
+            A[u] = base + (k0 + u) * kBlock + threadIdx.x;
+            in[u] = A[u] < M;
+            ka[u] = in[u] ? cell_key[A[u]] : 0ull;
+            kp[u] = (in[u] && A[u] > 0) ? cell_key[A[u] - 1] : 0ull;
+            fr[u] = (in[u] && batched) ? cell_frame[A[u]] : 0u;
         }
-        heads[A] = head ? 1 : 0;
-        if (head) last = (int32_t)A;
+        uint32_t s0[kR], s1[kR], s2[kR];
+        float d2[kR];
+#pragma unroll
+        for (int u = 0; u < kR; ++u) {
+            nr[u] = in[u] && A[u] > 0 && next_is_near(g, kp[u], ka[u]);  // same x: same frame
+            s0[u] = nr[u] ? cell_start[A[u] - 1] : 0u;
+            s1[u] = nr[u] ? cell_start[A[u]] : 0u;
+            s2[u] = nr[u] ? cell_start[A[u] + 1] : 0u;
+            d2[u] = (nr[u] && batched) ? frames[fr[u]].d2 : d2_one;
+        }
+        float4 pa[kR], pb[kR];
+#pragma unroll
+        for (int u = 0; u < kR; ++u) {
+            pa[u] = nr[u] ? spts[s0[u]] : make_float4(0.f, 0.f, 0.f, 0.f);
+            pb[u] = nr[u] ? spts[s1[u]] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < kR; ++u) {
+            if (!in[u]) continue;
+            bool head = true;
+            if (nr[u])
+                head = !(joined(pa[u].x, pa[u].y, pa[u].z, pb[u], d2[u]) ||
+                         any_joined_1(spts, s0[u], s1[u], s1[u], s2[u], d2[u]));
+            heads[A[u]] = head ? 1 : 0;
+            if (head) last = (int32_t)A[u];
+        }
     }
     // block max of the last run start
 #pragma unroll
