@@ -209,3 +209,28 @@ def test_column_index_modes():
         assert np.array_equal(got, want), "%s: %s" % (tag, describe_mismatch(got, want))
         assert k == wk
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("offset", [1, 2, 3])
+def test_labels_into_unaligned_buffer(offset):
+    # the labels are first set to -1 with 16-byte stores when the caller's
+    # buffer allows, word by word otherwise; only kept clusters are written
+    # after.  A buffer at a 4-, 8- or 12-byte offset, with sentinels around
+    # it that must stay untouched, and size windows that keep everything,
+    # nothing, or some clusters.
+    import torch
+
+    import paper_2208_07678_amd as fec
+    xyz = synth.blobs_cloud(n=5003, n_blobs=8, seed=4)
+    n = xyz.shape[0]
+    x = torch.from_numpy(xyz).cuda()
+    for mn, mx in ((1, n), (n + 1, n + 5), (2, 600)):
+        say("unaligned labels offset", offset, "window", mn, mx)
+        buf = torch.full((n + 8,), 12345, dtype=torch.int32, device="cuda")
+        lab = buf[offset:offset + n]
+        fec.cluster_async(x, 0.5, mn, mx, labels=lab)
+        torch.cuda.synchronize()
+        got = buf.cpu().numpy()
+        want, _ = oracle.fec(xyz, 0.5, mn, mx)
+        assert np.array_equal(got[offset:offset + n], want)
+        assert (got[:offset] == 12345).all() and (got[offset + n:] == 12345).all()
