@@ -1170,11 +1170,15 @@ __device__ __forceinline__ int64_t xcd_block() {
     const uint32_t r = b % span;
     return (int64_t)(b - r) + (r % kXcds) * C + r / kXcds;
 }
-// Run lengths C of the two hooking kernels, measured on the 27 M map (near shell 2.34 -> 2.10 ms, far
-// shell 1.04 -> 0.98 ms) with batches of frames unchanged.  The far shell's
-// work list is sparse in the cells and gains less; whole eighths per XCD
-// (C = gridDim.x / 8) unbalance both shells on batches (near 0.44 -> 0.64 ms).
-constexpr uint32_t kXcdRunNear = 64;
+// Run lengths C of the two hooking kernels, measured on the 27 M map against
+// C = 1 (near shell 2.34 -> 2.10 ms with three cells loaded per column, far
+// shell 1.04 -> 0.98 ms with groups of 8 columns; with one cell per column,
+// C = 128 for the near shell measures 1.68 -> 1.63 ms against C = 64, and
+// the far shell is the same for C from 8 to 64), batches of frames
+// unchanged.  The far shell's work list is sparse in the cells and gains
+// less; whole eighths per XCD (C = gridDim.x / 8) unbalance both shells on
+// batches (near 0.44 -> 0.64 ms).
+constexpr uint32_t kXcdRunNear = 128;
 constexpr uint32_t kXcdRunFar = 16;
 
 // Union-find over cells.  Two roots are joined by hooking the one of higher
