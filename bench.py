@@ -552,8 +552,9 @@ def main():
         copy_probe(args.copy_probe)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(the multi-GPU slab decomposition is a design note, not code)" % args.gpus,
+        print("bench.py: the clustering runs on one GPU; --gpus %d is not supported "
+              "(splitting the map into slabs over several GPUs is described, not implemented)"
+              % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
