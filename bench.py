@@ -658,8 +658,8 @@ def main():
 
     # The stage's time per call covers all its launches: the sort stages run
     # once per radix pass (passes beyond the key's width return at once), the
-    # two hooking stages launch a large-cloud and a small-cloud form of which
-    # one returns at once.  Per working launch: the stage time per call over
+    # two hooking stages on clouds of 131,072 points or more launch a
+    # large-table and a small-table form of which one returns at once.  Per working launch: the stage time per call over
     # the working launches.
     passes = stats.get("radix_passes") or 0
     work_launches = passes if dominant.startswith("sort") else 1

@@ -2378,9 +2378,15 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     FEC_LAUNCH(kStRuns, k_runs1<<<(unsigned)ntiles, kBlock, 0, st>>>(
                             spts, cell_start, cell_key, heads, blkhead, frames, cell_frame, P));
     FEC_LAUNCH(kStRuns, k_runs2<<<(unsigned)ntiles, kBlock, 0, st>>>(heads, blkhead, cpar, P));
-    FEC_LAUNCH(kStHookNear, k_hook_near<false><<<nb_cells, kBlock, 0, st>>>(
-                                spts, cell_start, cell_key, col_key, col_cell, colgrid, colbits,
-                                frames, cell_frame, cpar, P));
+    // Each shell has a large-table and a small-table form; which one a call
+    // needs is known on the device only, so both are launched and the other
+    // returns at once.  Cells and work cells never outnumber points, so below
+    // the thresholds in points the large forms cannot be meant and are not
+    // launched (two launches fewer on small clouds).
+    if (n >= kNearSplitBelow)
+        FEC_LAUNCH(kStHookNear, k_hook_near<false><<<nb_cells, kBlock, 0, st>>>(
+                                    spts, cell_start, cell_key, col_key, col_cell, colgrid,
+                                    colbits, frames, cell_frame, cpar, P));
     FEC_LAUNCH(kStHookNear, k_hook_near<true><<<nb_cells, kBlock, 0, st>>>(
                                 spts, cell_start, cell_key, col_key, col_cell, colgrid, colbits,
                                 frames, cell_frame, cpar, P));
@@ -2388,10 +2394,10 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     FEC_LAUNCH(kStGiant, k_giant<<<(unsigned)nframes, 1024, 0, st>>>(cpar, frames, P));
     FEC_LAUNCH(kStWorkList, k_nongiant<<<nb_cells, kBlock, 0, st>>>(cpar, gbits, work, frames,
                                                                      cell_frame, P));
-    // both forms are launched; the one whose case the work list is not returns
-    FEC_LAUNCH(kStHookFar, k_hook_far<false><<<nb_cells, kBlock, 0, st>>>(
-                                spts, cell_start, cell_key, col_key, col_cell, colgrid, colbits,
-                                gbits, work, frames, cell_frame, cpar, P));
+    if (n >= (int64_t)kFarSplitBelow)
+        FEC_LAUNCH(kStHookFar, k_hook_far<false><<<nb_cells, kBlock, 0, st>>>(
+                                   spts, cell_start, cell_key, col_key, col_cell, colgrid,
+                                   colbits, gbits, work, frames, cell_frame, cpar, P));
     FEC_LAUNCH(kStHookFar, k_hook_far<true><<<nb_cells, kBlock, 0, st>>>(
                                 spts, cell_start, cell_key, col_key, col_cell, colgrid, colbits,
                                 gbits, work, frames, cell_frame, cpar, P));

@@ -84,9 +84,12 @@ def test_workspace_stats_and_profile():
     say(prof)
     assert st["n"] == xyz.shape[0] and st["finite_points"] == xyz.shape[0]
     assert 0 < st["cells"] <= xyz.shape[0] and st["status"] == 0
-    # the near shell launches its large-cloud and small-cloud forms (one of
-    # them returns at once)
-    assert prof["hook_near"][1] == 2 and prof["hook_near"][0] > 0
+    # the near shell launches only its small-table form when the cloud has
+    # fewer points than the split threshold (131,072), both forms otherwise
+    # (the one not meant for the table returns at once)
+    assert xyz.shape[0] < 131072
+    assert prof["hook_near"][1] == 1 and prof["hook_near"][0] > 0
+    assert prof["hook_far"][1] == 1
 
 
 def test_library_first_then_torch_in_fresh_process():
