@@ -4,14 +4,20 @@ For labels produced with the output convention of the clustering (each kept
 cluster named by its smallest point index, -1 for points of clusters whose
 size lies outside [min_size, max_size]):
 
-* partition / minimality: a kept label L satisfies 0 <= L <= i, point L
-  carries L itself, and L is the smallest index carrying L;
+* partition / minimality: no label is below -1, and the first point that
+  carries a kept label L is point L (so 0 <= L <= i for every carrier i,
+  and point L carries L itself);
 * size filter: every kept label is carried by between min_size and max_size
   points;
 * filter exactness: the filtered labelling equals the unfiltered one with
   clusters of out-of-range size masked to -1;
 * closure (with an ``oracle.Index``): both ends of every edge of the graph
-  carry the same label, checked on a sample of points.
+  carry the same label, checked on a sample of points (catches a split
+  cluster, not a merge);
+* components (with an ``oracle.Index``): for sampled seed points, the
+  breadth-first component of the seed in the graph has as many points as
+  the unfiltered labelling gives the seed's label, and its smallest index is
+  that label (catches merges and splits alike).
 
 Each check returns a list of human-readable problems (empty when it holds).
 """
@@ -22,27 +28,22 @@ import numpy as np
 
 
 def partition_problems(labels: np.ndarray, max_report: int = 5) -> list[str]:
+    """Labels that are not -1 or a valid cluster name: a value below -1, or a
+    kept label L whose first carrier is not point L.  The second condition is
+    the whole of partition and minimality: it means every point carrying L
+    has index >= L (so L <= i, and L < n), and point L carries L itself."""
     lab = np.asarray(labels, dtype=np.int64)
-    n = lab.shape[0]
     out = []
-    idx = np.arange(n)
-    bad_range = (lab < -1) | (lab > idx)
-    if bad_range.any():
-        w = np.nonzero(bad_range)[0][:max_report]
-        out.append("labels outside {-1} U [0, i] at %s" % w.tolist())
-        return out
-    kept = lab >= 0
-    roots = lab[kept]
-    self_ok = lab[roots] == roots
-    if not self_ok.all():
-        w = np.nonzero(kept)[0][~self_ok][:max_report]
-        out.append("label's own point does not carry it at %s" % w.tolist())
-    # minimality: the first occurrence of each kept label is the label itself
-    if kept.any():
+    neg = lab < -1
+    if neg.any():
+        out.append("labels below -1 at %s" % np.nonzero(neg)[0][:max_report].tolist())
+    kept = np.nonzero(lab >= 0)[0]
+    if kept.size:
         uniq, first = np.unique(lab[kept], return_index=True)
-        first_idx = idx[kept][first]
-        if not np.array_equal(uniq, first_idx):
-            out.append("a kept label is not the smallest index carrying it")
+        bad = kept[first] != uniq
+        if bad.any():
+            out.append("kept labels whose first carrier is another point: %s"
+                       % uniq[bad][:max_report].tolist())
     return out
 
 
@@ -81,6 +82,30 @@ def closure_problems(index, labels: np.ndarray, sample: np.ndarray) -> list[str]
     if bad:
         return ["%d edges from sampled points join different labels" % bad]
     return []
+
+
+def component_problems(index, unfiltered: np.ndarray, seeds, cap: int) -> list[str]:
+    """Seeds whose true component (breadth-first search, stopped after
+    ``cap`` points) does not match the unfiltered labelling: another size
+    (clusters merged or split) or another smallest index.  Seeds whose
+    component is larger than ``cap`` are compared only by being larger."""
+    u = np.asarray(unfiltered, dtype=np.int64)
+    sizes = np.bincount(u[u >= 0], minlength=u.shape[0])
+    out = []
+    for s in np.asarray(seeds, dtype=np.int64):
+        c, m = index.component(int(s), int(cap))
+        lab = int(u[s])
+        have = int(sizes[lab]) if lab >= 0 else 0
+        if c > cap:
+            if have <= cap:
+                out.append("seed %d: component larger than %d, label %d has %d points"
+                           % (s, cap, lab, have))
+        elif (c, m) != (have, lab):
+            out.append("seed %d: component size %d min %d, labelling size %d label %d"
+                       % (s, c, m, have, lab))
+        if len(out) >= 5:
+            break
+    return out
 
 
 def count_kept(labels: np.ndarray) -> int:
