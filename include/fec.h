@@ -197,7 +197,10 @@ int32_t fec_server_poll(fec_server *server, int64_t *tickets, int32_t *k, double
  * out[0] requests submitted, out[1] completed, out[2] batches launched,
  * out[3] queued now, out[4] slots busy now, out[5] most requests in one
  * batch, out[6] most batches in flight at once, out[7] points per slot,
- * out[8] bytes per slot.  Returns the number of values written (<= 9).
+ * out[8] bytes per slot, out[9] requests re-queued to run alone (their
+ * batch's stacked grid needed a key wider than 64 bits, so the whole batch
+ * was refused; alone each gets its own result).  Returns the number of
+ * values written (<= 10).
  */
 int32_t fec_server_stats(const fec_server *server, int64_t *out, int32_t max_out);
 

@@ -8,6 +8,7 @@ Contents:
 
 * ``fec``            -- the C++ oracle (``fec_oracle.cpp``): Alg. 1's
   point-wise loop over a kd-tree, then canonical labels and the size filter.
+* ``fec_both``       -- one run, filtered and unfiltered labels together.
 * ``fec_raw``        -- the raw Alg. 1 label values after any number of steps.
 * ``Index``          -- the oracle's kd-tree kept alive for sampled checks on
   clouds too large to cluster in full (component of one point, neighbours
@@ -63,6 +64,10 @@ def _load():
                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                   ctypes.c_void_p]
     lib.oracle_fec_ex.restype = ctypes.c_int64
+    lib.oracle_fec_full.argtypes = [f32p, ctypes.c_int64, ctypes.c_float, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.oracle_fec_full.restype = ctypes.c_int64
     lib.oracle_index_new.argtypes = [f32p, ctypes.c_int64, ctypes.c_float]
     lib.oracle_index_new.restype = ctypes.c_void_p
     lib.oracle_index_free.argtypes = [ctypes.c_void_p]
@@ -105,6 +110,22 @@ def fec(xyz, d: float, min_size: int = 1, max_size: int = 2**31 - 1, flags: int 
     if k < 0:
         raise ValueError("oracle_fec rejected its arguments")
     return out, int(k)
+
+
+def fec_both(xyz, d: float, min_size: int = 1, max_size: int = 2**31 - 1):
+    """One run of the exact clustering, two outputs: (filtered labels, kept
+    clusters, unfiltered canonical labels, number of clusters)."""
+    a = _as_xyz(xyz)
+    n = a.shape[0]
+    out = np.empty(n, dtype=np.int32)
+    canon = np.empty(n, dtype=np.int32)
+    nc = ctypes.c_int64(0)
+    k = _load().oracle_fec_full(a.ctypes.data, n, ctypes.c_float(d), int(min_size),
+                                int(max_size), 0, 0, out.ctypes.data, canon.ctypes.data,
+                                ctypes.byref(nc))
+    if k < 0:
+        raise ValueError("oracle_fec rejected its arguments")
+    return out, int(k), canon, int(nc.value)
 
 
 def fec_raw(xyz, d: float, steps: int | None = None, flags: int = 0):

@@ -295,10 +295,14 @@ int32_t oracle_fec_raw(const float *xyz, int64_t n, float d, int64_t steps, int3
 // Full clustering: canonical labels (smallest member index, -1 when the
 // cluster size is outside [min_size, max_size]).  Returns the number of
 // kept clusters, or -1 on bad arguments.  th_max > 0: the capped variant
-// (measurement only).
-int64_t oracle_fec_ex(const float *xyz, int64_t n, float d, int32_t min_size, int32_t max_size,
-                      int32_t flags, int64_t th_max, int32_t *labels_out) {
+// (measurement only).  When canon_out is not null it also receives the
+// canonical labels before the size filter, and *ncomp the number of
+// clusters (one loop serves both outputs).
+int64_t oracle_fec_full(const float *xyz, int64_t n, float d, int32_t min_size,
+                        int32_t max_size, int32_t flags, int64_t th_max, int32_t *labels_out,
+                        int32_t *canon_out, int64_t *ncomp) {
     if (n < 0 || !d_ok(d) || min_size > max_size || th_max < 0) return -1;
+    if (ncomp) *ncomp = 0;
     if (n == 0) return 0;
     std::vector<int64_t> lab(n);
     fec_loop(xyz, n, d, n, flags, lab.data(), th_max);
@@ -310,14 +314,24 @@ int64_t oracle_fec_ex(const float *xyz, int64_t n, float d, int32_t min_size, in
         ++size[l];
     }
     int64_t lo = min_size < 1 ? 1 : min_size;
-    int64_t k = 0;
-    for (int64_t l = 0; l < n + 2; ++l)
+    int64_t k = 0, all = 0;
+    for (int64_t l = 0; l < n + 2; ++l) {
         if (size[l] > 0 && size[l] >= lo && size[l] <= max_size) ++k;
+        if (size[l] > 0) ++all;
+    }
     for (int64_t i = 0; i < n; ++i) {
         int64_t l = lab[i];
         labels_out[i] = (size[l] >= lo && size[l] <= max_size) ? (int32_t)first[l] : -1;
+        if (canon_out) canon_out[i] = (int32_t)first[l];
     }
+    if (ncomp) *ncomp = all;
     return k;
+}
+
+int64_t oracle_fec_ex(const float *xyz, int64_t n, float d, int32_t min_size, int32_t max_size,
+                      int32_t flags, int64_t th_max, int32_t *labels_out) {
+    return oracle_fec_full(xyz, n, d, min_size, max_size, flags, th_max, labels_out, nullptr,
+                           nullptr);
 }
 
 // Full clustering as Alg. 1 with the readings above (no cap).

@@ -318,7 +318,8 @@ def cluster_batch(xyz, offsets, d, min_size=1, max_size=2**31 - 1, *, workspace=
 
 
 SERVER_STATS_FIELDS = ["submitted", "completed", "batches", "queued", "slots_busy",
-                       "max_batch_frames", "max_in_flight", "slot_points", "slot_bytes"]
+                       "max_batch_frames", "max_in_flight", "slot_points", "slot_bytes",
+                       "requeued"]
 
 
 class Server:

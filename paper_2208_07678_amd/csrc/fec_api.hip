@@ -132,14 +132,11 @@ int32_t fec_cluster_async(const float *xyz, int64_t n, float d, int32_t min_size
     int32_t rc = check_args(xyz, n, d, min_size, max_size, labels_out);
     if (rc != FEC_OK) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (n == 0) {
+    if (n == 0) {  // k = 0, written on the stream (no host synchronisation)
         if (k_out) {
-            int32_t zero = 0;
-            if (hipMemcpyAsync(k_out, &zero, sizeof zero, hipMemcpyHostToDevice, st) !=
-                hipSuccess)
-                return fail(FEC_EDEVICE, "hipMemcpyAsync of k failed");
-            if (hipStreamSynchronize(st) != hipSuccess)
-                return fail(FEC_EDEVICE, "hipStreamSynchronize failed");
+            const hipError_t e = fec::launch_set_count(k_out, 0, st);
+            if (e != hipSuccess)
+                return fail(FEC_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
         }
         return ok();
     }

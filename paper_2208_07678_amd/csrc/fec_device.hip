@@ -2240,6 +2240,16 @@ __global__ __launch_bounds__(kBlock) void k_error_fill(int32_t *__restrict__ lab
         labels[i] = -1;
 }
 
+// The count of an empty call (nothing else to enqueue).
+__global__ void k_set_count(int32_t *__restrict__ k_out, int32_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *k_out = v;
+}
+
+hipError_t launch_set_count(int32_t *k_out, int32_t v, hipStream_t st) {
+    k_set_count<<<1, 64, 0, st>>>(k_out, v);
+    return hipGetLastError();
+}
+
 // Per frame: kept clusters, or the frame's (else the call's) failure status.
 __global__ __launch_bounds__(kBlock) void k_finish(const Params *__restrict__ P,
                                                    const Frame *__restrict__ frames, int nframes,

@@ -234,6 +234,10 @@ constexpr int32_t kDefaultStreamBlocks = 4096;
 Tuning tuning();
 void set_tuning(Tuning t);
 
+// Enqueues one kernel that writes v to *k_out (the count of an empty call:
+// no host-side write, so the asynchronous form stays capturable).
+hipError_t launch_set_count(int32_t *k_out, int32_t v, hipStream_t stream);
+
 // Enqueues the whole pipeline.  Returns hipSuccess or the first launch error.
 hipError_t launch_pipeline(const CallArgs &a, void *ws, const Layout &L, hipStream_t stream,
                            Timer *timer);

@@ -42,6 +42,7 @@ struct Req {
     int32_t min_size, max_size;
     int32_t *labels;
     Clock::time_point t_submit;
+    bool alone;  // runs as a batch of its own (its batch was refused as a whole)
 };
 
 // Batch table, laid out in one buffer (host pinned copy -> device):
@@ -155,6 +156,7 @@ struct fec_server {
     int64_t next_ticket = 0;
     int64_t n_submitted = 0, n_completed = 0, n_batches = 0;
     int64_t max_batch_frames = 0, max_in_flight = 0;
+    int64_t n_requeued = 0;
     int32_t error = FEC_OK;
 };
 
@@ -200,6 +202,26 @@ int32_t retire(fec_server *S, Slot &s, bool block) {
         S->error = FEC_EDEVICE;
         return FEC_EDEVICE;
     }
+    // A batch's frames share one stacked grid, and its key can need more
+    // than 64 bits although each frame's alone fits (frames far apart in
+    // extent): the whole batch then comes back FEC_ERANGE.  Its requests go
+    // back to the head of the queue, in order, each to run alone, where the
+    // result is its own (FEC_ERANGE again only if the frame itself is).
+    if (s.reqs.size() > 1) {
+        bool all_range = true;
+        for (size_t i = 0; i < s.reqs.size(); ++i) all_range &= s.k_host[i] == FEC_ERANGE;
+        if (all_range) {
+            for (auto it = s.reqs.rbegin(); it != s.reqs.rend(); ++it) {
+                Req r = *it;
+                r.alone = true;
+                S->queue.push_front(r);
+            }
+            S->n_requeued += (int64_t)s.reqs.size();
+            s.reqs.clear();
+            s.busy = false;
+            return 0;
+        }
+    }
     const auto now = Clock::now();
     int32_t c = 0;
     for (size_t i = 0; i < s.reqs.size(); ++i) {
@@ -220,9 +242,11 @@ int32_t launch(fec_server *S, Slot &s) {
     int64_t pts = 0;
     while (!S->queue.empty() && (int32_t)batch.size() < S->slot_frames &&
            pts + S->queue.front().n <= S->slot_points) {
+        if (S->queue.front().alone && !batch.empty()) break;  // it runs on its own
         pts += S->queue.front().n;
         batch.push_back(S->queue.front());
         S->queue.pop_front();
+        if (batch.back().alone) break;
     }
     if (batch.empty()) return 0;
     const int32_t F = (int32_t)batch.size();
@@ -379,7 +403,7 @@ int32_t fec_server_submit(fec_server *S, const float *xyz, int64_t n, float d, i
     const int32_t rc = check_request(n, d, min_size, max_size, xyz, labels_out);
     if (rc != FEC_OK) return rc;
     if (n > S->slot_points) return FEC_ENOMEM;  // never fits a slot
-    Req r{S->next_ticket++, xyz, n, d, min_size, max_size, labels_out, Clock::now()};
+    Req r{S->next_ticket++, xyz, n, d, min_size, max_size, labels_out, Clock::now(), false};
     S->queue.push_back(r);
     ++S->n_submitted;
     if (ticket) *ticket = r.ticket;
@@ -443,16 +467,17 @@ int32_t fec_server_stats(const fec_server *S, int64_t *out, int32_t max_out) {
     if (!S || !out || max_out <= 0) return FEC_EINVAL;
     int64_t busy = 0;
     for (auto &s : S->slots) busy += s.busy ? 1 : 0;
-    const int64_t v[9] = {S->n_submitted,
-                          S->n_completed,
-                          S->n_batches,
-                          (int64_t)S->queue.size(),
-                          busy,
-                          S->max_batch_frames,
-                          S->max_in_flight,
-                          S->slot_points,
-                          (int64_t)S->slot_bytes};
-    const int32_t c = max_out < 9 ? max_out : 9;
+    const int64_t v[10] = {S->n_submitted,
+                           S->n_completed,
+                           S->n_batches,
+                           (int64_t)S->queue.size(),
+                           busy,
+                           S->max_batch_frames,
+                           S->max_in_flight,
+                           S->slot_points,
+                           (int64_t)S->slot_bytes,
+                           S->n_requeued};
+    const int32_t c = max_out < 10 ? max_out : 10;
     for (int32_t i = 0; i < c; ++i) out[i] = v[i];
     return c;
 }

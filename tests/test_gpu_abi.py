@@ -111,3 +111,37 @@ def test_library_first_then_torch_in_fresh_process():
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240)
     assert r.returncode == 0, r.stderr[-2000:]
     assert r.stdout.strip().splitlines()[-1] == "[0, 0, 2] 2"
+
+
+def test_empty_call_writes_its_count_on_the_stream_and_captures():
+    # n == 0 enqueues one kernel that writes k = 0 (no host copy, no
+    # synchronisation), so even the empty call can be captured in a graph
+    import torch
+
+    import paper_2208_07678_amd as fec
+    dev = torch.device("cuda:0")
+    empty = torch.zeros((0, 3), dtype=torch.float32, device=dev)
+    labels = torch.empty(0, dtype=torch.int32, device=dev)
+    k_out = torch.full((1,), 9, dtype=torch.int32, device=dev)
+    ws = fec.new_workspace(0, dev)
+    fec.cluster_async(empty, 0.5, 1, 10, labels=labels, k_out=k_out, workspace=ws)
+    torch.cuda.synchronize()
+    assert int(k_out.item()) == 0
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fec.cluster_async(empty, 0.5, 1, 10, labels=labels, k_out=k_out, workspace=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    say("graph capture of an empty call")
+    with torch.cuda.graph(graph):
+        fec.cluster_async(empty, 0.5, 1, 10, labels=labels, k_out=k_out, workspace=ws)
+    torch.cuda.synchronize()
+    for r in range(3):
+        k_out.fill_(9)
+        torch.cuda.synchronize()
+        say("graph replay", r)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert int(k_out.item()) == 0, r

@@ -125,17 +125,22 @@ def test_wide_grid_pair_mode():
     _check(x, 1e-3, 10, 10, "wide grid, size filter")
 
 
-def test_tile_over_lds_capacity():
-    # one column tile holding more cells than the LDS union-find takes
-    # (global union-find inside the tile), near the percolation threshold
+def test_tall_sparse_columns_near_percolation():
+    # a narrow box 20 m tall (32 x 32 columns of about 290 cells each) at
+    # about 0.07 points per cell and 1.5 neighbours per point: columns
+    # with long gaps, so both shells locate the cells in reach of a cell by
+    # the tall-column seek rather than from the column's first cell
     x = synth.random_cloud(20000, extent=(2.2, 2.2, 20.0), seed=12)
-    _check(x, 0.12, 1, 20000, "tile over capacity")
-    _check(x, 0.12, 3, 50, "tile over capacity, filtered")
+    _check(x, 0.12, 1, 20000, "tall sparse columns")
+    _check(x, 0.12, 3, 50, "tall sparse columns, filtered")
 
 
-def test_tile_borders_dense_plane():
-    # a dense plane spanning many column tiles, d such that every cell is
-    # occupied: all joins cross tile borders somewhere
+def test_dense_plane_one_cell_layer():
+    # a plane of about one point per cell over 462 x 462 columns, about 9
+    # neighbours per point (above the plane's percolation threshold): one
+    # giant component spanning the plane with small pieces around it, which
+    # exercises the giant-component bitmap and the far shell's backward
+    # pairs towards it
     x = synth.random_cloud(200000, extent=(40.0, 40.0, 0.05), seed=13)
     _check(x, 0.15, 1, 200000, "dense plane")
 

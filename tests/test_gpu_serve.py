@@ -1,8 +1,7 @@
 """GPU tests of the serving engine (fec_server_* through the C ABI).
 
 Each request's labels and count must equal the single-cloud call on that
-cloud alone (and the oracle's, where it is checked), whatever it was batched
-with: tolerance 0.
+cloud alone and the oracle's, whatever it was batched with: tolerance 0.
 """
 
 import numpy as np
@@ -63,9 +62,37 @@ def test_mix_equals_alone_and_oracle():
         alone, ka = gpu_cluster(x, d, mn, mx) if x.shape[0] else (np.zeros(0, np.int32), 0)
         assert np.array_equal(got, alone), "request %d: %s" % (i, describe_mismatch(got, alone))
         assert k == ka, (i, k, ka)
-        if x.shape[0] <= 3000:
-            want, wk = oracle.fec(x, d, mn, mx)
-            assert np.array_equal(got, want) and k == wk, i
+        want, wk = oracle.fec(x, d, mn, mx)
+        assert np.array_equal(got, want), "request %d: %s" % (i, describe_mismatch(got, want))
+        assert k == wk, (i, k, wk)
+    srv.close()
+
+
+def test_batch_refused_as_a_whole_reruns_each_request_alone():
+    # Three 2-point requests, each 10^6 m long along its own axis with d = 1 mm:
+    # alone each grid key has about 31 bits; stacked into one batch the key
+    # needs about 93, so the batch is refused (FEC_ERANGE) as a whole.  The
+    # engine re-runs each request alone, where it gets its own result.
+    import torch
+    reqs = []
+    for ax in range(3):
+        x = np.zeros((2, 3), dtype=np.float32)
+        x[1, ax] = 1.0e6
+        reqs.append(x)
+    srv = _server(budget_mb=64, nslots=1, frames=8)
+    ts = [torch.from_numpy(x).to("cuda:0") for x in reqs]
+    tickets = [srv.submit(t, 1e-3, 1, 10) for t in ts]
+    done = {t: (lab, k) for t, lab, k, _ in srv.drain()}
+    st = srv.stats()
+    say("server stats", st)
+    assert st["requeued"] == 3 and st["completed"] == 3
+    for i, x in enumerate(reqs):
+        lab, k = done[tickets[i]]
+        got = lab.cpu().numpy()
+        alone, ka = gpu_cluster(x, 1e-3, 1, 10)
+        want, wk = oracle.fec(x, 1e-3, 1, 10)
+        assert np.array_equal(got, alone) and k == ka, (i, got, alone, k, ka)
+        assert np.array_equal(got, want) and k == wk == 2, (i, got, want, k, wk)
     srv.close()
 
 

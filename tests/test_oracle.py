@@ -278,3 +278,15 @@ def test_rejects_bad_arguments():
             oracle.fec(x, d)
     with pytest.raises(ValueError):
         oracle.fec(x, 0.5, 5, 2)
+
+
+def test_fec_both_equals_two_single_runs():
+    # one loop, two outputs: the filtered labels and count equal a filtered
+    # run, the unfiltered labels and cluster count equal a run without bounds
+    for seed, (mn, mx) in enumerate([(1, 10**9), (3, 40), (50, 60), (1, 1)]):
+        xyz = synth.blobs_cloud(n=3000, n_blobs=6, seed=70 + seed)
+        filt, k, unf, nc = oracle.fec_both(xyz, 0.4, mn, mx)
+        f2, k2 = oracle.fec(xyz, 0.4, mn, mx)
+        u2, n2 = oracle.fec(xyz, 0.4, 1, 2**31 - 1)
+        assert np.array_equal(filt, f2) and k == k2
+        assert np.array_equal(unf, u2) and nc == n2
