@@ -89,6 +89,29 @@ int32_t fec_cluster_async(const float *xyz, int64_t n, float d, int32_t min_size
                           size_t workspace_bytes, void *stream);
 
 /*
+ * No-allocation form, for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The same computation as fec_cluster_async, enqueued on
+ * `stream`, but its workspace is the library's own static device array of
+ * FEC_NOALLOC_SCRATCH_BYTES bytes (one per GPU, held until the process
+ * ends), so the call allocates nothing; the caller passes only the inputs
+ * and outputs (DEVICE pointers as above; k_out may be NULL).
+ *   n          at most FEC_NOALLOC_MAX_POINTS; larger n returns FEC_EINVAL
+ *              (with the host-side checks of fec_cluster), nothing launched.
+ * Returns FEC_OK once enqueued, FEC_EDEVICE when the scratch array's device
+ * address cannot be obtained or a launch fails.  Every call on one GPU
+ * shares that GPU's array, and each call overwrites what the previous left
+ * there: calls that overlap on one GPU (on different streams, or from
+ * several host threads) race and give wrong results.  Order them on one
+ * stream, or synchronise between them.
+ */
+#define FEC_NOALLOC_MAX_POINTS 524288
+#define FEC_NOALLOC_SCRATCH_BYTES (64u << 20)
+int32_t fec_cluster_noalloc(const float *xyz, int64_t n, float d, int32_t min_size,
+                            int32_t max_size, int32_t *labels_out, int32_t *k_out,
+                            void *stream);
+
+/*
  * Batched form: many independent clouds ("frames") in one call, each with its
  * own threshold and size bounds -- the result for every frame is exactly what
  * fec_cluster_async returns for that frame alone (same Sec. 2.2 / Eq. (1) /

@@ -21,7 +21,8 @@ import ctypes
 import os
 
 __all__ = [
-    "cluster", "cluster_async", "workspace_bytes", "workspace_stats", "FecError",
+    "cluster", "cluster_async", "cluster_noalloc", "workspace_bytes", "workspace_stats",
+    "FecError", "NOALLOC_MAX_POINTS",
     "cluster_batch", "cluster_batch_async", "batch_workspace_bytes", "pack_frames", "Server",
     "profile_enable", "profile_read", "profile_reset", "stage_names", "lib_path",
     "FEC_OK", "FEC_EINVAL", "FEC_ERANGE", "FEC_ENOMEM", "FEC_EDEVICE",
@@ -32,6 +33,7 @@ FEC_EINVAL = -1
 FEC_ERANGE = -2
 FEC_ENOMEM = -3
 FEC_EDEVICE = -4
+NOALLOC_MAX_POINTS = 524288  # FEC_NOALLOC_MAX_POINTS of include/fec.h
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libfec_hip.so")
@@ -59,6 +61,7 @@ def _load():
         "fec_cluster": ([vp, i64, f32, i32, i32, vp], i32),
         "fec_workspace_bytes": ([i64], ctypes.c_size_t),
         "fec_cluster_async": ([vp, i64, f32, i32, i32, vp, vp, vp, ctypes.c_size_t, vp], i32),
+        "fec_cluster_noalloc": ([vp, i64, f32, i32, i32, vp, vp, vp], i32),
         "fec_cluster_batch_async": ([vp, i64, i32, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t,
                                      vp], i32),
         "fec_batch_workspace_bytes": ([i64, i32], ctypes.c_size_t),
@@ -92,7 +95,8 @@ def _load():
 
 
 EXPORTED = [
-    "fec_cluster", "fec_workspace_bytes", "fec_cluster_async", "fec_set_stream", "fec_release",
+    "fec_cluster", "fec_workspace_bytes", "fec_cluster_async", "fec_cluster_noalloc",
+    "fec_set_stream", "fec_release",
     "fec_cluster_batch_async", "fec_batch_workspace_bytes", "fec_server_slot_bytes",
     "fec_server_create", "fec_server_slot_points", "fec_server_submit", "fec_server_pump",
     "fec_server_poll", "fec_server_stats", "fec_server_destroy", "fec_tuning_set",
@@ -195,6 +199,35 @@ def cluster(xyz, d: float, min_size: int = 1, max_size: int = 2**31 - 1, *,
     if k < 0:
         raise FecError(k, "device-side status %d" % k)
     return labels, k
+
+
+def cluster_noalloc(xyz, d: float, min_size: int = 1, max_size: int = 2**31 - 1, *,
+                    labels, k_out, stream=None):
+    """Enqueues the clustering with the library's static scratch array as its
+    workspace (fec_cluster_noalloc): nothing is allocated, so ``labels``
+    (int32 [n]) and ``k_out`` (int32 [1]) are the caller's device tensors.
+    At most NOALLOC_MAX_POINTS points; calls that overlap on one GPU race."""
+    torch = _torch()
+    _check_xyz(xyz)
+    n = xyz.shape[0]
+    dev = xyz.device
+    for name, t in (("labels", labels), ("k_out", k_out)):
+        if (not isinstance(t, torch.Tensor) or t.device != dev or t.dtype != torch.int32
+                or not t.is_contiguous()):
+            raise ValueError("%s must be a contiguous int32 tensor on %s" % (name, dev))
+    if labels.numel() < n or k_out.numel() < 1:
+        raise ValueError("labels needs %d entries and k_out one" % n)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        rc = _load().fec_cluster_noalloc(ctypes.c_void_p(xyz.data_ptr()), n, float(d),
+                                         int(min_size), int(max_size),
+                                         ctypes.c_void_p(labels.data_ptr()),
+                                         ctypes.c_void_p(k_out.data_ptr()),
+                                         ctypes.c_void_p(stream.cuda_stream))
+    if rc != FEC_OK:
+        _raise(rc)
+    return labels, k_out
 
 
 def set_tuning(cell_blocks: int = 0, stream_blocks: int = 0) -> None:

@@ -105,6 +105,43 @@ struct EventTimer final : fec::Timer {
 std::mutex g_mu;
 EventTimer g_timer;
 
+// ----------------------------------------------------------------- no-allocation form
+// The workspace of fec_cluster_noalloc: a static device array, one copy per
+// GPU.  In host code its name only stands for the symbol; its device address
+// on the current GPU comes from hipGetSymbolAddress, taken once per device
+// and kept.
+constexpr size_t kScratchBytes = FEC_NOALLOC_SCRATCH_BYTES;
+static_assert(fec::make_layout(FEC_NOALLOC_MAX_POINTS).total <= kScratchBytes,
+              "the scratch array holds the workspace of the largest call it admits");
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of the scratch array on the current GPU.
+int32_t scratch_address(void **out) {
+    int dev = -1;
+    const hipError_t e0 = hipGetDevice(&dev);
+    if (e0 != hipSuccess) return fail(FEC_EDEVICE, "hipGetDevice failed: %s", hipGetErrorString(e0));
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fail(FEC_EDEVICE, "device %d beyond the %d the library tracks", dev,
+                    kMaxScratchDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return fail(FEC_EDEVICE, "hipGetSymbolAddress of the scratch array failed: %s",
+                        hipGetErrorString(e));
+        if ((reinterpret_cast<uintptr_t>(p) & 255u) != 0)
+            return fail(FEC_EDEVICE, "scratch array is not 256-byte aligned");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return FEC_OK;
+}
+
 // ----------------------------------------------------------------- blocking form state
 struct Cached {
     void *ws = nullptr;
@@ -159,6 +196,45 @@ int32_t fec_cluster_async(const float *xyz, int64_t n, float d, int32_t min_size
     {
         std::lock_guard<std::mutex> lock(g_mu);
         e = fec::launch_pipeline(a, workspace, L, st, g_timer.mask ? &g_timer : nullptr);
+    }
+    if (e != hipSuccess) return fail(FEC_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+int32_t fec_cluster_noalloc(const float *xyz, int64_t n, float d, int32_t min_size,
+                            int32_t max_size, int32_t *labels_out, int32_t *k_out,
+                            void *stream) {
+    int32_t rc = check_args(xyz, n, d, min_size, max_size, labels_out);
+    if (rc != FEC_OK) return rc;
+    if (n > FEC_NOALLOC_MAX_POINTS)
+        return fail(FEC_EINVAL, "n=%lld exceeds the no-allocation form's %d points",
+                    (long long)n, FEC_NOALLOC_MAX_POINTS);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (n == 0) {
+        if (k_out) {
+            const hipError_t e = fec::launch_set_count(k_out, 0, st);
+            if (e != hipSuccess)
+                return fail(FEC_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+        }
+        return ok();
+    }
+    void *ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc != FEC_OK) return rc;
+    const fec::Layout L = fec::make_layout(n);
+    fec::CallArgs a{};
+    a.xyz = xyz;
+    a.n = n;
+    a.nframes = 1;
+    a.d = d;
+    a.min_size = min_size;
+    a.max_size = max_size;
+    a.labels_out = labels_out;
+    a.k_out = k_out;
+    hipError_t e;
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        e = fec::launch_pipeline(a, ws, L, st, g_timer.mask ? &g_timer : nullptr);
     }
     if (e != hipSuccess) return fail(FEC_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return ok();

@@ -106,17 +106,17 @@ struct Layout {
     int32_t bbox_per_frame;  // blocks of the bounding-box reduction per frame
 };
 
-inline uint64_t next_pow2(uint64_t v) {
+constexpr uint64_t next_pow2(uint64_t v) {
     uint64_t p = 1;
     while (p < v) p <<= 1;
     return p;
 }
 
-inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Bounding-box blocks per frame: about kBboxBlocks in all, at most one per
 // 1024 points of an average frame, at least one.
-inline int32_t bbox_blocks_per_frame(int64_t n, int32_t nframes) {
+constexpr int32_t bbox_blocks_per_frame(int64_t n, int32_t nframes) {
     const int64_t f = nframes > 0 ? nframes : 1;
     int64_t b = kBboxBlocks / f;
     const int64_t need = (n / f + 1023) / 1024;
@@ -124,7 +124,7 @@ inline int32_t bbox_blocks_per_frame(int64_t n, int32_t nframes) {
     return (int32_t)(b < 1 ? 1 : b);
 }
 
-inline Layout make_layout(int64_t n, int32_t nframes = 1) {
+constexpr Layout make_layout(int64_t n, int32_t nframes = 1) {
     Layout L{};
     L.nframes = nframes;
     L.bbox_per_frame = bbox_blocks_per_frame(n, nframes);

@@ -77,6 +77,28 @@ def test_host_side_argument_checks(fec):
     assert rc == fec.FEC_OK
 
 
+def test_noalloc_host_side_checks(fec):
+    # the no-allocation form's size limit and argument checks come before
+    # any device call; its scratch array holds the largest call it admits
+    lib = fec.raw_lib()
+    buf = ctypes.c_void_p(0x1000)   # never dereferenced: checks fail first
+    hdr = open(HEADER).read()
+    lim = int(re.search(r"#define FEC_NOALLOC_MAX_POINTS (\d+)", hdr).group(1))
+    sb = re.search(r"#define FEC_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", hdr)
+    scratch = int(sb.group(1)) << int(sb.group(2))
+    assert lim == fec.NOALLOC_MAX_POINTS
+    assert 0 < fec.workspace_bytes(lim) <= scratch
+    for n, d, mn, mx in [(lim + 1, 0.5, 1, 5), (-1, 0.5, 1, 5), (10, 0.0, 1, 5),
+                         (10, float("nan"), 1, 5), (10, 0.5, 6, 5)]:
+        rc = lib.fec_cluster_noalloc(buf, n, ctypes.c_float(d), mn, mx, buf, None, None)
+        assert rc == fec.FEC_EINVAL, (n, d, mn, mx)
+        assert lib.fec_last_error()
+    rc = lib.fec_cluster_noalloc(None, 10, ctypes.c_float(0.5), 1, 5, buf, None, None)
+    assert rc == fec.FEC_EINVAL
+    # n == 0 with no k_out: nothing to do, no device touched
+    assert lib.fec_cluster_noalloc(None, 0, ctypes.c_float(0.5), 1, 5, None, None, None) == 0
+
+
 def test_cpu_tensors_are_refused(fec):
     import torch
     with pytest.raises(ValueError):
