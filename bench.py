@@ -11,7 +11,10 @@ in HBM before timing starts.  Prints one JSON line.
 The dominant kernel is timed live with HIP events recorded on the launch
 stream by the library; its algorithmic bytes per launch over its average
 duration give the roofline fraction against the 8 TB/s HBM peak.  The CPU
-oracle, single-threaded, is timed on a bounded prefix of the same map.
+oracle, single-threaded, clusters the same whole map once.  The same line
+carries the batched form on 64 frames (frames/s against 64 plain calls, and
+graph replay) and the serving engine on the Poisson request trace (saturated
+frames/s, p50/p99 latency at 400 requests/s against plain FIFO calls).
 """
 
 from __future__ import annotations
@@ -28,15 +31,30 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic HBM bytes per point of each stage (reads + writes the stage
-# must do at minimum; see the design notes for the derivation).
+# Algorithmic HBM bytes per point of each stage: the bytes the stage must
+# move at minimum, per the path's byte model (the design notes derive each).
 ALG_BYTES_PER_POINT = {
     "bbox": 12.0,        # read xyz
     "keys": 12.0 + 8.0,  # read xyz, write packed key
     "sort_hist": 8.0,     # read one 8-byte packed key per pass
     "sort_scatter": 16.0,  # read + write one 8-byte packed key per pass
     "gather": 8.0 + 12.0 + 16.0 + 4.0,  # read key, read xyz, write float4 + index
+    "cells": 8.0,        # the cell table: sorted keys read once, cell starts and keys written
+    # hooking: every point read once (16) plus parent initialisation and
+    # unions (12); the far shell visits only the cells outside the giant
+    # component, so its share is scaled by work cells / cells
+    "hook_near": 28.0,
+    "hook_far": 28.0,
     "final_labels": 4.0,  # write every label once (-1 pass); kept clusters' labels again
+}
+# The whole path per point (survey byte model of the specified pipeline with
+# 64-bit keys): the figure the path's algorithmic HBM fraction is taken on.
+PATH_ALG_BYTES_PER_POINT = 260.0
+# What bounds each stage in practice (the roof is HBM for all of them).
+LIMITER = {
+    "hook_near": "latency: chains of dependent loads and device-scope compare-and-swap",
+    "hook_far": "latency: chains of dependent loads and device-scope compare-and-swap",
+    "runs": "latency: dependent loads",
 }
 
 
@@ -51,14 +69,16 @@ def _cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(frames: int, runs: int = 3):
+def cpu_baseline(frames: int, runs: int = 3, xyz=None):
     """The oracle, single-threaded and pinned to one core, on the first
-    ``frames`` frames of the map: median of ``runs`` runs."""
+    ``frames`` frames of the map (all 200: the whole map, ``xyz`` when given):
+    median of ``runs`` runs."""
     import numpy as np  # noqa: F401
 
     import oracle
     import synth
-    xyz = synth.lidar_map(frames=list(range(frames)))
+    if xyz is None or frames < 200:
+        xyz = synth.lidar_map(frames=list(range(frames)))
     pinned = None
     try:
         allowed = sorted(os.sched_getaffinity(0))
@@ -81,10 +101,12 @@ def cpu_baseline(frames: int, runs: int = 3):
         "unit": "points/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": "first %d of 200 frames of the map (%d points), d=0.2, sizes 100..5e6; "
-                  "single-threaded C++ (Alg. 1 over a kd-tree) pinned to core %s, median of %d "
-                  "runs %.2f s, host %s, %d cores available" % (
-                      frames, xyz.shape[0], pinned, runs, dt, _cpu_model(),
+        "sample": "%s (%d points), d=0.2, sizes 100..5e6; "
+                  "single-threaded C++ (Alg. 1 over a kd-tree) pinned to core %s, %s %.2f s, "
+                  "host %s, %d cores available" % (
+                      "the whole map" if frames >= 200 else
+                      "first %d of 200 frames of the map" % frames, xyz.shape[0], pinned,
+                      "median of %d runs" % runs if runs > 1 else "one run", dt, _cpu_model(),
                       os.cpu_count() or 0),
         "seconds": dt,
         "clusters": k,
@@ -148,22 +170,26 @@ def path_traffic(workload: str, passes: int):
 
 
 def bench_batch(args) -> None:
+    print(json.dumps(batch_result(args)), flush=True)
+
+
+def batch_result(args) -> dict:
     """Frames/s of the batched form on the 64-frame batch, beside 64 plain
-    per-frame calls on the same resident frames (one JSON line)."""
+    per-frame calls on the same resident frames."""
     import torch
 
     import paper_2208_07678_amd as fec
     import synth
 
     t_gen = time.perf_counter()
-    frames, ds, mn, mx = synth.make_batch_config(args.workload)
+    frames, ds, mn, mx = synth.make_batch_config("batch64")
     t_gen = time.perf_counter() - t_gen
     nf = len(frames)
     dev = torch.device("cuda:0")
     xs = [torch.from_numpy(f).to(dev) for f in frames]
     xyz, offs = fec.pack_frames(xs)
     n = xyz.shape[0]
-    print("bench: workload %s %d frames n=%d generated in %.1f s" % (args.workload, nf, n, t_gen),
+    print("bench: workload batch64 %d frames n=%d generated in %.1f s" % (nf, n, t_gen),
           file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream(dev)
     labels = torch.empty(n, dtype=torch.int32, device=dev)
@@ -260,7 +286,7 @@ def bench_batch(args) -> None:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "frames": nf, "n_points": n,
+        "config": {"workload": "batch64", "frames": nf, "n_points": n,
                    "d_values": sorted(set(ds)), "min_size": mn, "max_size": mx,
                    "clusters_kept": int(sum(ks))},
         "sequential": {"ms_per_batch": seq_ms, "frames_per_s": nf / (seq_ms * 1e-3),
@@ -273,14 +299,18 @@ def bench_batch(args) -> None:
     }
     if args.stages:
         out["stage_ms_per_call"] = {s: round(v[0], 4) for s, v in prof_all.items()}
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_serve(args) -> None:
+    print(json.dumps(serve_result(args)), flush=True)
+
+
+def serve_result(args) -> dict:
     """The serving engine on a Poisson request stream, beside plain
-    per-request FIFO calls on the same trace (one JSON line): latency
-    percentiles at the stream's rate, and frames/s with every request
-    available at once (saturated)."""
+    per-request FIFO calls on the same trace: latency percentiles at the
+    stream's rate, and frames/s with every request available at once
+    (saturated)."""
     import numpy as np
     import torch
 
@@ -397,7 +427,7 @@ def bench_serve(args) -> None:
         "roofline": None,
         "cpu_baseline": None,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_sweep(args) -> None:
@@ -539,8 +569,12 @@ def main():
     ap.add_argument("--slots", type=int, default=2, help="serve: batch slots")
     ap.add_argument("--slot-frames", type=int, default=64, help="serve: requests per batch")
     ap.add_argument("--serve-budget-gb", type=int, default=16, help="serve: HBM budget")
-    ap.add_argument("--cpu-frames", type=int, default=30,
-                    help="map frames in the CPU-baseline sample (0 = skip)")
+    ap.add_argument("--cpu-frames", type=int, default=200,
+                    help="map frames in the CPU-baseline sample (200 = the whole map, one run; "
+                         "0 = skip)")
+    ap.add_argument("--extras", type=int, default=1,
+                    help="map27m: also run the batch64 and serve workloads into the same line "
+                         "(0 = map only)")
     ap.add_argument("--stages", action="store_true", help="also print a per-stage breakdown")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch shape with the autotuner before timing")
@@ -650,11 +684,21 @@ def main():
         blocking.append((time.perf_counter() - b0) * 1e3)
     call_ms = {"median": float(np.median(per_call)), "p99": float(np.percentile(per_call, 99)),
                "blocking_median": float(np.median(blocking))}
+    # whole path: the algorithmic fraction (path byte model over the call
+    # time) and, while the committed counter summary matches the sources,
+    # the measured HBM bytes of one call over the call's median event time
+    # (the stage events of the profiled call add their own gaps, so their
+    # sum is reported only as a breakdown)
     kernel_ms = sum(v[0] for v in prof_all.values())
     tb = path_traffic(args.workload, stats.get("radix_passes") or 0)
-    path = {"kernel_ms": kernel_ms, "hbm_bytes": tb,
-            "hbm_GBps": None if tb is None else tb / (kernel_ms * 1e-3) / 1e9,
-            "frac": None if tb is None else tb / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    call_s = call_ms["median"] * 1e-3
+    path = {"alg_bytes_per_point": PATH_ALG_BYTES_PER_POINT,
+            "alg_GBps": PATH_ALG_BYTES_PER_POINT * n / (ms_per_step * 1e-3) / 1e9,
+            "alg_frac": PATH_ALG_BYTES_PER_POINT * n / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "hbm_bytes": tb,
+            "hbm_GBps": None if tb is None else tb / call_s / 1e9,
+            "frac": None if tb is None else tb / call_s / 1e9 / HBM_PEAK_GBS,
+            "stage_event_ms_sum": kernel_ms}
 
     # The stage's time per call covers all its launches: the sort stages run
     # once per radix pass (passes beyond the key's width return at once), the
@@ -666,19 +710,36 @@ def main():
     avg_launch_ms = dom_ms / args.steps / max(work_launches, 1)
     # stages without a per-point byte model are reported against HBM with the
     # bytes of their cells' points read once (a lower bound)
-    bytes_per_launch = ALG_BYTES_PER_POINT.get(dominant, 16.0) * n
+    bpp = ALG_BYTES_PER_POINT.get(dominant, 16.0)
+    if dominant == "hook_far":
+        bpp *= (stats.get("work_cells") or 0) / max(stats.get("cells") or 1, 1)
+    bytes_per_launch = bpp * n
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, dominant),
-                "kernel": dominant, "avg_launch_ms": avg_launch_ms,
+                "kernel": dominant, "limiter": LIMITER.get(dominant, "hbm bandwidth"),
+                "avg_launch_ms": avg_launch_ms,
                 "launches_per_step": dom_launches / args.steps,
                 "working_launches_per_step": work_launches,
-                "alg_bytes_per_launch": bytes_per_launch}
+                "alg_bytes_per_point": bpp, "alg_bytes_per_launch": bytes_per_launch}
+
+    extras = {}
+    if args.extras and args.workload == "map27m":
+        del x, labels, ws
+        torch.cuda.empty_cache()
+        b = batch_result(args)
+        extras["batch64"] = {"frames_per_s": b["value"], "ms_per_batch": b["ms_per_step"],
+                             "frames": b["config"]["frames"], "n_points": b["config"]["n_points"],
+                             "plain_calls": b["sequential"], "graph_replay": b["graph_replay"],
+                             "dominant_kernel": b["roofline"]["kernel"]}
+        sv = serve_result(args)
+        extras["serve"] = {"config": sv["config"], "saturated": sv["saturated"],
+                           "poisson": sv["poisson"]}
 
     cpu = None
     if args.cpu_frames > 0 and args.workload == "map27m":
         print("bench: CPU oracle on %d frames ..." % args.cpu_frames, file=sys.stderr, flush=True)
-        cpu = cpu_baseline(args.cpu_frames)
+        cpu = cpu_baseline(args.cpu_frames, runs=1 if args.cpu_frames >= 200 else 3, xyz=xyz)
 
     out = {
         "metric": "points/s clustered (27M-pt map, % HBM peak)",
@@ -699,13 +760,14 @@ def main():
                    "mean_points_per_cell": n / max(stats.get("cells") or 1, 1),
                    "radix_passes": stats.get("radix_passes"),
                    "work_cells": stats.get("work_cells"),
-                   "launch_shape": list(fec.get_tuning()),
+                   "launch_config": dict(zip(("cell_blocks", "stream_blocks", "radix_bits", "hook_block"), fec.get_tuning())),
                    "autotuned": tuned is not None},
         "roofline": roofline,
         "call_ms": call_ms,
         "path": path,
         "cpu_baseline": cpu,
     }
+    out.update(extras)
     if args.stages:
         out["stage_ms_per_call"] = {s: round(v[1], 4) for s, v in per_launch.items()}
     print(json.dumps(out), flush=True)

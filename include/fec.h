@@ -272,14 +272,23 @@ void fec_profile_reset(void);
 int32_t fec_stage_count(void);
 
 /*
- * Launch shape (the autotuner's knobs; process-wide, applies to calls
- * enqueued afterwards): the most blocks of the per-cell grid-stride kernels
- * (default 4096) and of the per-point streaming kernels (default 4096); 0
- * restores a default.  Labels and counts do not depend on them.  Returns
- * FEC_OK, or FEC_EINVAL for values outside [0, 2^20].
+ * Launch configuration (the autotuner's knobs; process-wide, applies to
+ * calls enqueued afterwards):
+ *   cell_blocks    the most blocks of the per-cell grid-stride kernels
+ *                  (default 4096), in [0, 2^20];
+ *   stream_blocks  the most blocks of the per-point streaming kernels
+ *                  (default 4096), in [0, 2^20];
+ *   radix_bits     bits per radix-sort pass: 8, 9, 10 or 11 (default 9);
+ *                  wider digits take fewer passes over larger tables;
+ *   hook_block     threads per block of the hooking kernels: 64, 128 or
+ *                  256 (default 256).
+ * 0 restores a knob's default.  Labels and counts do not depend on any of
+ * them.  Returns FEC_OK, or FEC_EINVAL for a value outside its set.
  */
-int32_t fec_tuning_set(int32_t cell_blocks, int32_t stream_blocks);
-int32_t fec_tuning_get(int32_t *cell_blocks, int32_t *stream_blocks);
+int32_t fec_tuning_set(int32_t cell_blocks, int32_t stream_blocks, int32_t radix_bits,
+                       int32_t hook_block);
+int32_t fec_tuning_get(int32_t *cell_blocks, int32_t *stream_blocks, int32_t *radix_bits,
+                       int32_t *hook_block);
 const char *fec_stage_name(int32_t stage);
 
 #ifdef __cplusplus

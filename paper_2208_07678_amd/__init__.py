@@ -66,8 +66,8 @@ def _load():
                                      vp], i32),
         "fec_batch_workspace_bytes": ([i64, i32], ctypes.c_size_t),
         "fec_server_slot_bytes": ([i64, i32], ctypes.c_size_t),
-        "fec_tuning_set": ([i32, i32], i32),
-        "fec_tuning_get": ([vp, vp], i32),
+        "fec_tuning_set": ([i32, i32, i32, i32], i32),
+        "fec_tuning_get": ([vp, vp, vp, vp], i32),
         "fec_server_create": ([ctypes.c_size_t, i32, i32, vp], i32),
         "fec_server_slot_points": ([vp], i64),
         "fec_server_submit": ([vp, vp, i64, f32, i32, i32, vp, vp], i32),
@@ -230,17 +230,22 @@ def cluster_noalloc(xyz, d: float, min_size: int = 1, max_size: int = 2**31 - 1,
     return labels, k_out
 
 
-def set_tuning(cell_blocks: int = 0, stream_blocks: int = 0) -> None:
-    """Launch shape of later calls (0 = default); see ``paper_2208_07678_amd.tune``."""
-    rc = _load().fec_tuning_set(int(cell_blocks), int(stream_blocks))
+def set_tuning(cell_blocks: int = 0, stream_blocks: int = 0, radix_bits: int = 0,
+               hook_block: int = 0) -> None:
+    """Launch configuration of later calls (0 = a knob's default): grid sizes
+    of the per-cell and streaming kernels, radix-sort digit width, block size
+    of the hooking kernels; see ``paper_2208_07678_amd.tune``."""
+    rc = _load().fec_tuning_set(int(cell_blocks), int(stream_blocks), int(radix_bits),
+                                int(hook_block))
     if rc != FEC_OK:
         _raise(rc)
 
 
-def get_tuning() -> tuple[int, int]:
-    a, b = ctypes.c_int32(), ctypes.c_int32()
-    _load().fec_tuning_get(ctypes.byref(a), ctypes.byref(b))
-    return int(a.value), int(b.value)
+def get_tuning() -> tuple[int, int, int, int]:
+    """(cell_blocks, stream_blocks, radix_bits, hook_block) in force."""
+    v = [ctypes.c_int32() for _ in range(4)]
+    _load().fec_tuning_get(*[ctypes.byref(x) for x in v])
+    return tuple(int(x.value) for x in v)
 
 
 def batch_workspace_bytes(n_total: int, nframes: int) -> int:

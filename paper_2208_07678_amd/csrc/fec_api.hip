@@ -375,19 +375,29 @@ void fec_profile_reset(void) {
     }
 }
 
-int32_t fec_tuning_set(int32_t cell_blocks, int32_t stream_blocks) {
+int32_t fec_tuning_set(int32_t cell_blocks, int32_t stream_blocks, int32_t radix_bits,
+                       int32_t hook_block) {
     if (cell_blocks < 0 || stream_blocks < 0 || cell_blocks > (1 << 20) ||
         stream_blocks > (1 << 20))
-        return fail(FEC_EINVAL, "tuning values outside [0, 2^20]");
+        return fail(FEC_EINVAL, "block counts outside [0, 2^20]");
+    if (radix_bits != 0 && (radix_bits < fec::kMinRadixBits || radix_bits > fec::kMaxRadixBits))
+        return fail(FEC_EINVAL, "radix_bits=%d not in {0, 8, 9, 10, 11}", radix_bits);
+    if (hook_block != 0 && hook_block != 64 && hook_block != 128 && hook_block != 256)
+        return fail(FEC_EINVAL, "hook_block=%d not in {0, 64, 128, 256}", hook_block);
     fec::set_tuning({cell_blocks ? cell_blocks : fec::kDefaultCellBlocks,
-                     stream_blocks ? stream_blocks : fec::kDefaultStreamBlocks});
+                     stream_blocks ? stream_blocks : fec::kDefaultStreamBlocks,
+                     radix_bits ? radix_bits : fec::kDefaultRadixBits,
+                     hook_block ? hook_block : fec::kDefaultHookBlock});
     return ok();
 }
 
-int32_t fec_tuning_get(int32_t *cell_blocks, int32_t *stream_blocks) {
+int32_t fec_tuning_get(int32_t *cell_blocks, int32_t *stream_blocks, int32_t *radix_bits,
+                       int32_t *hook_block) {
     const fec::Tuning t = fec::tuning();
     if (cell_blocks) *cell_blocks = t.cell_blocks;
     if (stream_blocks) *stream_blocks = t.stream_blocks;
+    if (radix_bits) *radix_bits = t.radix_bits;
+    if (hook_block) *hook_block = t.hook_block;
     return ok();
 }
 

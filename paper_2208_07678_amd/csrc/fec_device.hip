@@ -301,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ parti
                                                  const int32_t *__restrict__ min_arr,
                                                  const int32_t *__restrict__ max_arr, float d_one,
                                                  int32_t min_one, int32_t max_one,
-                                                 uint64_t colgrid_cap) {
+                                                 uint64_t colgrid_cap, int radix_bits) {
     __shared__ int64_t s_tmp[kBlock / 64];
     __shared__ int32_t s_bad;
     const int wave = threadIdx.x >> 6, lane = __lane_id();
@@ -456,7 +456,8 @@ __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ parti
     P->key_shift = P->pair_mode ? 0 : ib;
     if (kb > 64 && P->status == kStatusOk) P->status = kStatusRange;
     if (nframes == 1 && F0.status != kStatusOk && P->status == kStatusOk) P->status = F0.status;
-    P->npasses = P->status == kStatusOk ? (kb + kRadixBits - 1) / kRadixBits : 0;
+    P->radix_bits = radix_bits;
+    P->npasses = P->status == kStatusOk ? (kb + radix_bits - 1) / radix_bits : 0;
 }
 
 // Cell key: cx, then cy, then cz.  The cells of one column (cx, cy) are
@@ -536,23 +537,26 @@ __device__ __forceinline__ int64_t xcd_block_eighths() {
 }
 
 // ------------------------------------------------------------- 4. sort
-// Stable LSD radix sort of the packed (key, index) words, kRadixBits per
-// pass, reduce-then-scan: (1) each tile of kTile words counts its digits,
-// (2) one block per digit turns the per-tile counts (digit-major) into the
-// position of every tile's run of that digit, counted from the digit's first
-// word, and the digit's total, (3) each tile
+// Stable LSD radix sort of the packed (key, index) words, RB bits per pass
+// (RB from 8 to 11, a launch-time choice: fewer passes against larger
+// per-tile tables), reduce-then-scan: (1) each tile of kTile words counts
+// its digits, (2) one block per digit turns the per-tile counts
+// (digit-major) into the position of every tile's run of that digit,
+// counted from the digit's first word, and the digit's total, (3) each tile
 // ranks its words stably, stages them in LDS in digit order and writes each
 // digit's run to its position.  Tiles are independent in every step.  The
 // digits' global bases come from the per-digit totals of step (2), scanned
-// by every scatter block (256 values), so no earlier kernel has to count
-// digits over the whole array.
+// by every scatter block, so no earlier kernel has to count digits over the
+// whole array.  A thread owns R / kBlock consecutive digits where a step
+// works per digit.
 
 // Digit and stable in-wave rank of item k of this wave (lanes with equal
 // digits are "peers"; the rank counts peers on lower lanes).
+template <int RB>
 __device__ __forceinline__ uint64_t digit_peers(uint32_t dg, bool valid) {
     uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
+    for (int b = 0; b < RB; ++b) {
         const bool bit = (dg >> b) & 1u;
         const uint64_t bb = __ballot(bit);
         peers &= bit ? bb : ~bb;
@@ -560,18 +564,38 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t dg, bool valid) {
     return peers;
 }
 
+// Exclusive scan over R values held DPT = R / kBlock per thread (thread t
+// holds digits t*DPT .. t*DPT+DPT-1): v[] becomes the exclusive prefix of
+// each; returns nothing, total in `total`.
+template <int DPT>
+__device__ __forceinline__ void block_excl_scan_multi(uint32_t (&v)[DPT], uint32_t *s_tmp,
+                                                      uint32_t &total) {
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) sum += v[q];
+    uint32_t run = block_excl_scan(sum, s_tmp, total);
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+        const uint32_t x = v[q];
+        v[q] = run;
+        run += x;
+    }
+}
+
 // (1) per-tile digit counts, stored digit-major: th[dg * ntiles + tile].
+template <int RB>
 __global__ __launch_bounds__(kBlock) void k_sort_hist(const uint64_t *__restrict__ src,
                                                       const Params *__restrict__ P, int pass,
                                                       int64_t n, int64_t ntiles,
                                                       uint32_t *__restrict__ th) {
+    constexpr int R = 1 << RB, DPT = R / kBlock;
     if (pass >= P->npasses || P->status != kStatusOk) return;
-    __shared__ uint32_t s_cnt[kBlock / 64][kRadix];
+    __shared__ uint32_t s_cnt[kBlock / 64][R];
     const int tid = threadIdx.x, wave = tid >> 6, lane = __lane_id();
-    for (int i = tid; i < (kBlock / 64) * kRadix; i += kBlock) (&s_cnt[0][0])[i] = 0;
+    for (int i = tid; i < (kBlock / 64) * R; i += kBlock) (&s_cnt[0][0])[i] = 0;
     __syncthreads();
     const int64_t tile = blockIdx.x;
-    const int shift = P->key_shift + pass * kRadixBits;
+    const int shift = P->key_shift + pass * RB;
     const int64_t base = tile * kTile + (int64_t)wave * (64 * kItems);
     uint64_t v[kItems];
 #pragma unroll
@@ -581,25 +605,30 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(const uint64_t *__restrict
     }
     // counts only (no ranks): one LDS atomic add per word, into the wave's
     // own row; lanes adding to one counter are serialised by the LDS, which
-    // still costs far less than the eight ballots of a stable rank
+    // still costs far less than the ballots of a stable rank
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const bool valid = base + k * 64 + lane < n;
-        const uint32_t dg = (uint32_t)(v[k] >> shift) & (kRadix - 1);
+        const uint32_t dg = (uint32_t)(v[k] >> shift) & (R - 1);
         if (valid) atomicAdd(&s_cnt[wave][dg], 1u);
     }
     __syncthreads();
-    uint32_t c = 0;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) c += s_cnt[w][tid];
-    th[(int64_t)tid * ntiles + tile] = c;
+    for (int q = 0; q < DPT; ++q) {
+        const int dg = q * kBlock + tid;  // coalesced rows of th per q
+        uint32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) c += s_cnt[w][dg];
+        th[(int64_t)dg * ntiles + tile] = c;
+    }
 }
 
 // (2) one block per digit: exclusive scan of the digit's per-tile counts
 // (positions relative to the digit's first word) and the digit's total,
 // published for the scatter blocks, which add the digits' bases themselves.
-__global__ __launch_bounds__(kBlock) void k_sort_scan(Params *__restrict__ P, int pass,
-                                                      int64_t ntiles, uint32_t *__restrict__ th) {
+__global__ __launch_bounds__(kBlock) void k_sort_scan(const Params *__restrict__ P, int pass,
+                                                      int64_t ntiles, uint32_t *__restrict__ th,
+                                                      uint32_t *__restrict__ dtot) {
     if (pass >= P->npasses || P->status != kStatusOk) return;
     __shared__ uint32_t s_tmp[kBlock / 64];
     __shared__ uint32_t s_carry;
@@ -631,38 +660,48 @@ __global__ __launch_bounds__(kBlock) void k_sort_scan(Params *__restrict__ P, in
         if (tid == 0) s_carry = carry + tot;
         __syncthreads();
     }
-    if (tid == 0) P->hist[pass][d] = s_carry;
+    if (tid == 0) dtot[(int64_t)pass * kMaxRadix + d] = s_carry;
 }
 
 // (3) stable scatter of one tile.
-// Four waves per SIMD: its LDS allows four blocks per CU, and 129 registers
-// would allow three (one 8-byte spill at 128; scatter 0.59 -> 0.55 ms per map
-// call).
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_sort_scatter(const uint64_t *__restrict__ src,
-                                                         uint64_t *__restrict__ dst,
-                                                         const uint32_t *__restrict__ srcv,
-                                                         uint32_t *__restrict__ dstv,
-                                                         const Params *__restrict__ P, int pass,
-                                                         int64_t n, int64_t ntiles,
-                                                         const uint32_t *__restrict__ th) {
+// Waves per SIMD: as many as the LDS allows blocks per CU (four at 8-bit
+// digits, where 129 registers would allow three: one 8-byte spill at 128;
+// scatter 0.59 -> 0.55 ms per map call).
+constexpr int scatter_waves(int rb) { return rb == 8 ? 4 : (rb <= 10 ? 3 : 2); }
+
+template <int RB>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(scatter_waves(RB)))) void
+k_sort_scatter(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
+               const uint32_t *__restrict__ srcv, uint32_t *__restrict__ dstv,
+               const Params *__restrict__ P, int pass, int64_t n, int64_t ntiles,
+               const uint32_t *__restrict__ th, const uint32_t *__restrict__ dtot) {
+    constexpr int R = 1 << RB, DPT = R / kBlock;
     if (pass >= P->npasses || P->status != kStatusOk) return;
-    __shared__ uint32_t s_cnt[kBlock / 64][kRadix];
-    __shared__ uint32_t s_base[kRadix];
-    __shared__ uint32_t s_local[kRadix];
+    // s_cnt: per wave and digit, the count of the wave's words, then where
+    // they go in the tile's LDS buffer; s_base: where the tile's run of each
+    // digit goes in the output, then that minus the run's place in the
+    // buffer (so buffer slot j goes to s_base[digit] + j)
+    __shared__ uint32_t s_cnt[kBlock / 64][R];
+    __shared__ uint32_t s_base[R];
     __shared__ uint64_t s_buf[kTile];  // keys in digit order (values after them in pair mode)
     __shared__ uint32_t s_tmp[kBlock / 64];
     const int tid = threadIdx.x, wave = tid >> 6, lane = __lane_id();
-    for (int i = tid; i < (kBlock / 64) * kRadix; i += kBlock) (&s_cnt[0][0])[i] = 0;
+    for (int i = tid; i < (kBlock / 64) * R; i += kBlock) (&s_cnt[0][0])[i] = 0;
     const int64_t tile = blockIdx.x;
     {
         // this tile's position within each digit, plus the digit's base (the
-        // totals of all smaller digits)
+        // totals of all smaller digits); thread t owns digits t*DPT ..
+        uint32_t tv[DPT];
+#pragma unroll
+        for (int q = 0; q < DPT; ++q) tv[q] = dtot[(int64_t)pass * kMaxRadix + tid * DPT + q];
         uint32_t tot;
-        const uint32_t base = block_excl_scan(P->hist[pass][tid], s_tmp, tot);
-        s_base[tid] = base + th[(int64_t)tid * ntiles + tile];
+        block_excl_scan_multi<DPT>(tv, s_tmp, tot);
+#pragma unroll
+        for (int q = 0; q < DPT; ++q)
+            s_base[tid * DPT + q] = tv[q] + th[(int64_t)(tid * DPT + q) * ntiles + tile];
     }
     __syncthreads();
-    const int shift = P->key_shift + pass * kRadixBits;
+    const int shift = P->key_shift + pass * RB;
     const bool pair = P->pair_mode != 0;
     const int64_t base = tile * kTile + (int64_t)wave * (64 * kItems);
 
@@ -676,24 +715,41 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const bool valid = base + k * 64 + lane < n;
-        const uint32_t dg = (uint32_t)(v[k] >> shift) & (kRadix - 1);
-        const uint64_t peers = digit_peers(dg, valid);
+        const uint32_t dg = (uint32_t)(v[k] >> shift) & (R - 1);
+        const uint64_t peers = digit_peers<RB>(dg, valid);
         const uint32_t below = (uint32_t)__popcll(peers & lanemask_lt());
         const uint32_t prev = s_cnt[wave][dg];
         rk[k] = prev + below;
         if (valid && below == 0) s_cnt[wave][dg] = prev + (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    // per digit (thread = digit): wave offsets inside the tile, tile count
-    uint32_t run = 0;
+    {
+        // per digit: wave offsets inside the tile, then the tile's exclusive
+        // scan over digits (where each digit's run starts in the tile),
+        // folded into the wave offsets and the output base
+        uint32_t tv[DPT];
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) {
-        const uint32_t c = s_cnt[w][tid];
-        s_cnt[w][tid] = run;
-        run += c;
+        for (int q = 0; q < DPT; ++q) {
+            const int dg = tid * DPT + q;
+            uint32_t run = 0;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) {
+                const uint32_t c = s_cnt[w][dg];
+                s_cnt[w][dg] = run;
+                run += c;
+            }
+            tv[q] = run;
+        }
+        uint32_t tot;
+        block_excl_scan_multi<DPT>(tv, s_tmp, tot);
+#pragma unroll
+        for (int q = 0; q < DPT; ++q) {
+            const int dg = tid * DPT + q;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) s_cnt[w][dg] += tv[q];
+            s_base[dg] -= tv[q];  // modulo 2^32; adding the slot restores it
+        }
     }
-    uint32_t tot;
-    s_local[tid] = block_excl_scan(run, s_tmp, tot);
     __syncthreads();
     // stage the tile in LDS in digit order, then write each digit's run
     // contiguously; in pair mode the values follow through the same buffer
@@ -701,8 +757,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     for (int k = 0; k < kItems; ++k) {
         const int64_t e = base + k * 64 + lane;
         if (e < n) {
-            const uint32_t dg = (uint32_t)(v[k] >> shift) & (kRadix - 1);
-            s_buf[s_local[dg] + s_cnt[wave][dg] + rk[k]] = v[k];
+            const uint32_t dg = (uint32_t)(v[k] >> shift) & (R - 1);
+            s_buf[s_cnt[wave][dg] + rk[k]] = v[k];
         }
     }
     __syncthreads();
@@ -715,8 +771,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         pos[i] = 0xFFFFFFFFu;
         if (j < tile_n) {
             const uint64_t w = s_buf[j];
-            const uint32_t dg = (uint32_t)(w >> shift) & (kRadix - 1);
-            const uint64_t p = (uint64_t)s_base[dg] + (uint32_t)(j - s_local[dg]);
+            const uint32_t dg = (uint32_t)(w >> shift) & (R - 1);
+            const uint64_t p = (uint64_t)(uint32_t)(s_base[dg] + (uint32_t)j);
             if (p < (uint64_t)n) {
                 pos[i] = (uint32_t)p;
                 dst[p] = w;
@@ -730,8 +786,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         for (int k = 0; k < kItems; ++k) {
             const int64_t e = base + k * 64 + lane;
             if (e < n) {
-                const uint32_t dg = (uint32_t)(v[k] >> shift) & (kRadix - 1);
-                s_vbuf[s_local[dg] + s_cnt[wave][dg] + rk[k]] = srcv[e];
+                const uint32_t dg = (uint32_t)(v[k] >> shift) & (R - 1);
+                s_vbuf[s_cnt[wave][dg] + rk[k]] = srcv[e];
             }
         }
         __syncthreads();
@@ -1546,8 +1602,8 @@ constexpr int kNearGroup = 4;
 // candidate column (see k_hook_far's kFarSplitBelow).
 constexpr int64_t kNearSplitBelow = 131072;
 
-template <bool kSplit>
-__global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__ spts,
+template <bool kSplit, int BLK>
+__global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ spts,
                                                       const uint32_t *__restrict__ cell_start,
                                                       const uint64_t *__restrict__ cell_key,
                                                       const uint64_t *__restrict__ col_key,
@@ -1573,8 +1629,8 @@ __global__ __launch_bounds__(kBlock) void k_hook_near(const float4 *__restrict__
     if ((M < kNearSplitBelow) != kSplit) return;  // the other instance's case
     // kSplit: one task per (cell, group); every task loads the cell's own data
     constexpr int kTasks = kSplit ? kGroups : 1;
-    for (int64_t t = xcd_block<kXcdRunNear>() * kBlock + threadIdx.x; t < M * kTasks;
-         t += (int64_t)gridDim.x * kBlock) {
+    for (int64_t t = xcd_block<kXcdRunNear>() * BLK + threadIdx.x; t < M * kTasks;
+         t += (int64_t)gridDim.x * BLK) {
         const int32_t A = (int32_t)(t / kTasks);
         const int task = (int)(t % kTasks);
         // round 1
@@ -1872,8 +1928,8 @@ __device__ __forceinline__ bool is_giant(const uint64_t *__restrict__ gbits, uin
 // cell (the chip is full, and the tasks' repeated set-up would cost more).
 constexpr uint32_t kFarSplitBelow = 131072;
 
-template <bool kSplit>
-__global__ __launch_bounds__(kBlock) void k_hook_far(const float4 *__restrict__ spts,
+template <bool kSplit, int BLK>
+__global__ __launch_bounds__(BLK) void k_hook_far(const float4 *__restrict__ spts,
                                                       const uint32_t *__restrict__ cell_start,
                                                       const uint64_t *__restrict__ cell_key,
                                                       const uint64_t *__restrict__ col_key,
@@ -1910,8 +1966,8 @@ __global__ __launch_bounds__(kBlock) void k_hook_far(const float4 *__restrict__ 
     constexpr uint32_t kGroups = 24 / kG;
     constexpr uint32_t kTasks = kSplit ? kGroups : 1;
     const uint64_t ntask = (uint64_t)nwork * kTasks;
-    for (uint64_t t = (uint64_t)xcd_block<kXcdRunFar>() * kBlock + threadIdx.x; t < ntask;
-         t += (uint64_t)gridDim.x * kBlock) {
+    for (uint64_t t = (uint64_t)xcd_block<kXcdRunFar>() * BLK + threadIdx.x; t < ntask;
+         t += (uint64_t)gridDim.x * BLK) {
         const uint32_t wi = (uint32_t)(t / kTasks);
         const int task = (int)(t % kTasks);
         const int32_t A = (int32_t)work[wi];
@@ -2269,16 +2325,22 @@ __global__ __launch_bounds__(kBlock) void k_finish(const Params *__restrict__ P,
 namespace {
 std::atomic<int32_t> g_cell_blocks{kDefaultCellBlocks};
 std::atomic<int32_t> g_stream_blocks{kDefaultStreamBlocks};
+std::atomic<int32_t> g_radix_bits{kDefaultRadixBits};
+std::atomic<int32_t> g_hook_block{kDefaultHookBlock};
 }  // namespace
 
 Tuning tuning() {
     return Tuning{g_cell_blocks.load(std::memory_order_relaxed),
-                  g_stream_blocks.load(std::memory_order_relaxed)};
+                  g_stream_blocks.load(std::memory_order_relaxed),
+                  g_radix_bits.load(std::memory_order_relaxed),
+                  g_hook_block.load(std::memory_order_relaxed)};
 }
 
 void set_tuning(Tuning t) {
     g_cell_blocks.store(t.cell_blocks, std::memory_order_relaxed);
     g_stream_blocks.store(t.stream_blocks, std::memory_order_relaxed);
+    g_radix_bits.store(t.radix_bits, std::memory_order_relaxed);
+    g_hook_block.store(t.hook_block, std::memory_order_relaxed);
 }
 
 const char *stage_name(int s) {
@@ -2288,6 +2350,36 @@ const char *stage_name(int s) {
         "compress_1", "giant",     "work_list",  "hook_far",    "compress_2",   "final_cells",
         "final_labels", "finish"};
     return (s >= 0 && s < kNumStages) ? names[s] : "";
+}
+
+// The radix passes at RB bits per digit: passes beyond the device-side count
+// return at once (the pair-mode fallback can need up to a full 64-bit key).
+template <int RB>
+static hipError_t launch_sort(uint64_t *keys0, uint64_t *keys1, uint32_t *vals0, uint32_t *vals1,
+                              const Params *P, int64_t n, int64_t ntiles, uint32_t *th,
+                              uint32_t *dtot, hipStream_t st, Timer *timer) {
+    constexpr int kPasses = (64 + RB - 1) / RB;
+    for (int pass = 0; pass < kPasses; ++pass) {
+        const uint64_t *src = (pass & 1) ? keys1 : keys0;
+        uint64_t *dst = (pass & 1) ? keys0 : keys1;
+        const uint32_t *srcv = (pass & 1) ? vals1 : vals0;
+        uint32_t *dstv = (pass & 1) ? vals0 : vals1;
+        hipError_t e;
+        if (timer) timer->begin(kStSortHist, st);
+        k_sort_hist<RB><<<(unsigned)ntiles, kBlock, 0, st>>>(src, P, pass, n, ntiles, th);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (timer) timer->end(kStSortHist, st);
+        if (timer) timer->begin(kStSortScan, st);
+        k_sort_scan<<<1u << RB, kBlock, 0, st>>>(P, pass, ntiles, th, dtot);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (timer) timer->end(kStSortScan, st);
+        if (timer) timer->begin(kStSort, st);
+        k_sort_scatter<RB><<<(unsigned)ntiles, kBlock, 0, st>>>(src, dst, srcv, dstv, P, pass, n,
+                                                              ntiles, th, dtot);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (timer) timer->end(kStSort, st);
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipStream_t st,
@@ -2307,6 +2399,7 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     uint32_t *vals0 = reinterpret_cast<uint32_t *>(w + L.vals0);
     uint32_t *vals1 = reinterpret_cast<uint32_t *>(w + L.vals1);
     uint32_t *th = reinterpret_cast<uint32_t *>(w + L.th);
+    uint32_t *dtot = reinterpret_cast<uint32_t *>(w + L.dtot);
     float4 *spts = reinterpret_cast<float4 *>(w + L.spts);
     uint32_t *sorig = reinterpret_cast<uint32_t *>(w + L.sorig);
     uint32_t *cell_start = reinterpret_cast<uint32_t *>(w + L.cell_start);
@@ -2342,9 +2435,10 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
         keys_pf = keys_pf < 1 ? 1 : keys_pf;
     }
     const int nb_finish = (nframes + kBlock - 1) / kBlock;
-    // Passes beyond the device-side count return at once; the pair-mode
-    // fallback can need up to a full 64-bit key.
-    const int max_passes = kMaxPasses;
+    const int radix_bits = tn.radix_bits < kMinRadixBits
+                               ? kMinRadixBits
+                               : (tn.radix_bits > kMaxRadixBits ? kMaxRadixBits : tn.radix_bits);
+    const int hook_block = tn.hook_block == 64 || tn.hook_block == 128 ? tn.hook_block : 256;
 
 #define FEC_LAUNCH(stage, ...)                         \
     do {                                               \
@@ -2360,19 +2454,18 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     FEC_LAUNCH(kStPlan, k_plan<<<1, kBlock, 0, st>>>(partials, bbox_pf, P, frames, nframes, n,
                                                       args.offsets, args.d_arr, args.min_arr,
                                                       args.max_arr, args.d, args.min_size,
-                                                      args.max_size, L.colgrid_cap));
+                                                      args.max_size, L.colgrid_cap, radix_bits));
     FEC_LAUNCH(kStKeys, k_keys<<<(unsigned)(nframes * keys_pf), kBlock, 0, st>>>(
                             xyz, P, frames, keys_pf, keys0, vals0));
-    for (int pass = 0; pass < max_passes; ++pass) {
-        const uint64_t *src = (pass & 1) ? keys1 : keys0;
-        uint64_t *dst = (pass & 1) ? keys0 : keys1;
-        const uint32_t *srcv = (pass & 1) ? vals1 : vals0;
-        uint32_t *dstv = (pass & 1) ? vals0 : vals1;
-        FEC_LAUNCH(kStSortHist,
-                   k_sort_hist<<<(unsigned)ntiles, kBlock, 0, st>>>(src, P, pass, n, ntiles, th));
-        FEC_LAUNCH(kStSortScan, k_sort_scan<<<kRadix, kBlock, 0, st>>>(P, pass, ntiles, th));
-        FEC_LAUNCH(kStSort, k_sort_scatter<<<(unsigned)ntiles, kBlock, 0, st>>>(
-                                src, dst, srcv, dstv, P, pass, n, ntiles, th));
+    {
+        hipError_t e = hipSuccess;
+        switch (radix_bits) {
+            case 8: e = launch_sort<8>(keys0, keys1, vals0, vals1, P, n, ntiles, th, dtot, st, timer); break;
+            case 9: e = launch_sort<9>(keys0, keys1, vals0, vals1, P, n, ntiles, th, dtot, st, timer); break;
+            case 10: e = launch_sort<10>(keys0, keys1, vals0, vals1, P, n, ntiles, th, dtot, st, timer); break;
+            default: e = launch_sort<11>(keys0, keys1, vals0, vals1, P, n, ntiles, th, dtot, st, timer); break;
+        }
+        if (e != hipSuccess) return e;
     }
     FEC_LAUNCH(kStGather, k_gather<<<(unsigned)ntiles, kBlock, 0, st>>>(
                               xyz, keys0, keys1, vals0, vals1, colbits, P, spts, sorig,
@@ -2393,24 +2486,36 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     // returns at once.  Cells and work cells never outnumber points, so below
     // the thresholds in points the large forms cannot be meant and are not
     // launched (two launches fewer on small clouds).
-    if (n >= kNearSplitBelow)
-        FEC_LAUNCH(kStHookNear, k_hook_near<false><<<nb_cells, kBlock, 0, st>>>(
-                                    spts, cell_start, cell_key, col_key, col_cell, colgrid,
-                                    colbits, frames, cell_frame, cpar, P));
-    FEC_LAUNCH(kStHookNear, k_hook_near<true><<<nb_cells, kBlock, 0, st>>>(
-                                spts, cell_start, cell_key, col_key, col_cell, colgrid, colbits,
-                                frames, cell_frame, cpar, P));
+#define FEC_HOOK_NEAR(SPLIT, BLK)                                                          \
+    FEC_LAUNCH(kStHookNear, k_hook_near<SPLIT, BLK><<<nb_cells, BLK, 0, st>>>(               \
+                                spts, cell_start, cell_key, col_key, col_cell, colgrid,      \
+                                colbits, frames, cell_frame, cpar, P))
+#define FEC_HOOK_FAR(SPLIT, BLK)                                                           \
+    FEC_LAUNCH(kStHookFar, k_hook_far<SPLIT, BLK><<<nb_cells, BLK, 0, st>>>(                 \
+                               spts, cell_start, cell_key, col_key, col_cell, colgrid,       \
+                               colbits, gbits, work, frames, cell_frame, cpar, P))
+    if (n >= kNearSplitBelow) {
+        if (hook_block == 64) FEC_HOOK_NEAR(false, 64);
+        else if (hook_block == 128) FEC_HOOK_NEAR(false, 128);
+        else FEC_HOOK_NEAR(false, 256);
+    }
+    if (hook_block == 64) FEC_HOOK_NEAR(true, 64);
+    else if (hook_block == 128) FEC_HOOK_NEAR(true, 128);
+    else FEC_HOOK_NEAR(true, 256);
     FEC_LAUNCH(kStCompress1, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P));
     FEC_LAUNCH(kStGiant, k_giant<<<(unsigned)nframes, 1024, 0, st>>>(cpar, frames, P));
     FEC_LAUNCH(kStWorkList, k_nongiant<<<nb_cells, kBlock, 0, st>>>(cpar, gbits, work, frames,
                                                                      cell_frame, P));
-    if (n >= (int64_t)kFarSplitBelow)
-        FEC_LAUNCH(kStHookFar, k_hook_far<false><<<nb_cells, kBlock, 0, st>>>(
-                                   spts, cell_start, cell_key, col_key, col_cell, colgrid,
-                                   colbits, gbits, work, frames, cell_frame, cpar, P));
-    FEC_LAUNCH(kStHookFar, k_hook_far<true><<<nb_cells, kBlock, 0, st>>>(
-                                spts, cell_start, cell_key, col_key, col_cell, colgrid, colbits,
-                                gbits, work, frames, cell_frame, cpar, P));
+    if (n >= (int64_t)kFarSplitBelow) {
+        if (hook_block == 64) FEC_HOOK_FAR(false, 64);
+        else if (hook_block == 128) FEC_HOOK_FAR(false, 128);
+        else FEC_HOOK_FAR(false, 256);
+    }
+    if (hook_block == 64) FEC_HOOK_FAR(true, 64);
+    else if (hook_block == 128) FEC_HOOK_FAR(true, 128);
+    else FEC_HOOK_FAR(true, 256);
+#undef FEC_HOOK_NEAR
+#undef FEC_HOOK_FAR
     FEC_LAUNCH(kStCompress2, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P));
     FEC_LAUNCH(kStFinalCells, k_final_cells<<<nb_cells, kBlock, 0, st>>>(
                                   cpar, cell_start, sorig, csize, ccanon, P));

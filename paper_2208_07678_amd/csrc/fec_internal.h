@@ -11,9 +11,13 @@ namespace fec {
 constexpr int kBlock = 256;            // threads per block of the streaming kernels
 constexpr int kItems = 16;             // elements per thread in tiled kernels
 constexpr int kTile = kBlock * kItems; // elements per tile (sort, gather, cells)
-constexpr int kRadixBits = 8;
-constexpr int kRadix = 1 << kRadixBits;
-constexpr int kMaxPasses = (64 + kRadixBits - 1) / kRadixBits;
+// Radix sort digits: 8 to 11 bits per pass, chosen per call on the host
+// (the autotuner's knob); tables are sized for the widest.
+constexpr int kMinRadixBits = 8;
+constexpr int kMaxRadixBits = 11;
+constexpr int kMaxRadix = 1 << kMaxRadixBits;
+constexpr int kMaxPasses = (64 + kMinRadixBits - 1) / kMinRadixBits;
+constexpr int kDefaultRadixBits = 9;
 constexpr int kBboxBlocks = 1024;      // max blocks of the bounding-box reduction
 constexpr int kCellBlocks = 4096;      // grid of the grid-stride per-cell kernels
 // Dense column index: one entry per (cx, cy) when the plane has at most
@@ -71,6 +75,8 @@ struct Params {
     int32_t key_bits;     // bits sorted (grid key, plus one for non-finite points)
     int32_t idx_bits;     // bits of the point index packed below the key
     int32_t npasses;      // radix passes actually run
+    int32_t radix_bits;   // bits per radix pass
+    int32_t pad0;
     int32_t pair_mode;    // 0: one word (key << idx_bits | index); 1: key and index arrays
     int32_t key_shift;    // idx_bits in one-word mode, 0 in pair mode
     uint64_t idx_mask;
@@ -90,13 +96,12 @@ struct Params {
     uint64_t hmask;       // slots - 1
     uint64_t hcap;        // slots that fit in the dense index's memory (a power of two)
     unsigned long long counters[8];  // diagnostic event counts (counting builds only)
-    uint32_t hist[kMaxPasses][kRadix];   // digit totals of each pass
 };
 
 // ---------------------------------------------------------------- workspace
 struct Layout {
     size_t params, frames, partials, tile_cnt, tile_off;
-    size_t keys0, keys1, vals0, vals1, th;
+    size_t keys0, keys1, vals0, vals1, th, dtot;
     size_t spts, sorig, cell_start, cell_key, cpar, csize, ccanon;
     size_t col_key, col_cell, colgrid, colbits, heads, blkhead, gbits, work, cell_frame;
     uint64_t colgrid_cap;
@@ -146,7 +151,8 @@ constexpr Layout make_layout(int64_t n, int32_t nframes = 1) {
     L.keys1 = take(un * sizeof(uint64_t));
     L.vals0 = take(un * sizeof(uint32_t));
     L.vals1 = take(un * sizeof(uint32_t));
-    L.th = take((size_t)L.ntiles * kRadix * sizeof(uint32_t));
+    L.th = take((size_t)L.ntiles * kMaxRadix * sizeof(uint32_t));
+    L.dtot = take((size_t)kMaxPasses * kMaxRadix * sizeof(uint32_t));
     L.spts = take(un * sizeof(float4));
     L.sorig = take(un * sizeof(uint32_t));
     L.cell_start = take((un + 1) * sizeof(uint32_t));
@@ -228,9 +234,12 @@ struct CallArgs {
 struct Tuning {
     int32_t cell_blocks;
     int32_t stream_blocks;
+    int32_t radix_bits;  // bits per radix-sort pass (8 .. 11)
+    int32_t hook_block;  // threads per block of the hooking kernels (64, 128, 256)
 };
 constexpr int32_t kDefaultCellBlocks = kCellBlocks;
 constexpr int32_t kDefaultStreamBlocks = 4096;
+constexpr int32_t kDefaultHookBlock = 256;
 Tuning tuning();
 void set_tuning(Tuning t);
 

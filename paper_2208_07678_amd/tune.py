@@ -1,16 +1,26 @@
-"""Autotuner for the launch shape of the clustering kernels.
+"""Autotuner for the launch configuration of the clustering kernels.
 
-The per-cell kernels (near and far shells, compression, finalize) and the
-per-point streaming kernels are grid-stride loops; how many blocks they are
-launched with changes how work spreads over the chip's 256 CUs, not the
-result.  ``autotune`` times a set of candidate shapes on a representative
-cloud and keeps the fastest; the choice is cached in a JSON file keyed by
-GPU architecture and size bucket (log2 of the point count), and ``apply``
-sets the cached shape for a coming call.
+Four knobs change how the work is laid out on the chip, never the result:
+
+* ``cell_blocks``   -- blocks of the per-cell grid-stride kernels (near and
+  far shells, compression, finalize);
+* ``stream_blocks`` -- blocks of the per-point streaming kernels;
+* ``radix_bits``    -- bits per radix-sort pass (8 to 11: fewer passes over
+  larger per-tile tables);
+* ``hook_block``    -- threads per block of the hooking kernels (64, 128,
+  256).
+
+``autotune`` times candidate configurations on a representative cloud, checks
+that all give the same labels, and keeps the fastest: by default a coordinate
+search (each knob over its values with the others at the best so far, in the
+order radix_bits, hook_block, cell_blocks, stream_blocks), or every
+configuration of an explicit candidate list.  The choice is cached in a JSON
+file keyed by GPU architecture and size bucket (log2 of the point count), and
+``apply`` sets the cached configuration for a coming call.
 
     from paper_2208_07678_amd import tune
     best = tune.autotune(xyz, d, min_size, max_size)   # measures, caches
-    tune.apply(n)                                       # later: cached shape
+    tune.apply(n)                                       # later: cached choice
 
 Cache file: ``$FEC_TUNE_CACHE``, else ``~/.cache/fec_mi355x_tune.json``.
 """
@@ -24,7 +34,15 @@ import time
 
 from . import cluster_async, get_tuning, new_workspace, set_tuning
 
-CANDIDATES = [(c, s) for c in (1024, 2048, 4096, 8192, 16384) for s in (2048, 4096, 8192)]
+KNOBS = ("cell_blocks", "stream_blocks", "radix_bits", "hook_block")
+VALUES = {
+    "cell_blocks": (1024, 2048, 4096, 8192, 16384),
+    "stream_blocks": (2048, 4096, 8192),
+    "radix_bits": (8, 9, 10, 11),
+    "hook_block": (64, 128, 256),
+}
+SEARCH_ORDER = ("radix_bits", "hook_block", "cell_blocks", "stream_blocks")
+DEFAULT = (4096, 4096, 9, 256)
 
 
 def cache_path() -> str:
@@ -57,12 +75,19 @@ def _key(arch: str, n: int) -> str:
     return "%s/%d" % (arch, bucket(n))
 
 
-def record(arch: str, n: int, shape, ms: float, path: str | None = None) -> None:
-    """Stores the chosen shape for (arch, size bucket of n)."""
+def _full(cfg) -> tuple:
+    """A configuration as all four knobs (missing trailing knobs: defaults)."""
+    cfg = tuple(int(v) for v in cfg)
+    return cfg + DEFAULT[len(cfg):]
+
+
+def record(arch: str, n: int, cfg, ms: float, path: str | None = None) -> None:
+    """Stores the chosen configuration for (arch, size bucket of n)."""
     path = path or cache_path()
     c = _load_cache(path)
-    c[_key(arch, n)] = {"cell_blocks": int(shape[0]), "stream_blocks": int(shape[1]),
-                        "ms": float(ms), "n": int(n)}
+    e = dict(zip(KNOBS, _full(cfg)))
+    e.update({"ms": float(ms), "n": int(n)})
+    c[_key(arch, n)] = e
     os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
     tmp = path + ".tmp"
     with open(tmp, "w") as f:
@@ -71,32 +96,37 @@ def record(arch: str, n: int, shape, ms: float, path: str | None = None) -> None
 
 
 def lookup(arch: str, n: int, path: str | None = None):
-    """The cached (cell_blocks, stream_blocks) for (arch, size bucket of n), or None."""
+    """The cached configuration (four knobs) for (arch, size bucket of n), or None."""
     e = _load_cache(path or cache_path()).get(_key(arch, n))
-    return None if e is None else (int(e["cell_blocks"]), int(e["stream_blocks"]))
+    if e is None:
+        return None
+    return tuple(int(e.get(k, d)) for k, d in zip(KNOBS, DEFAULT))
 
 
-def apply(n: int, device="cuda:0", path: str | None = None) -> tuple[int, int]:
-    """Sets the cached shape for n points (the defaults when none is cached)."""
-    shape = lookup(_arch(device), n, path)
-    if shape is None:
-        set_tuning(0, 0)
-    else:
-        set_tuning(*shape)
+def apply(n: int, device="cuda:0", path: str | None = None) -> tuple:
+    """Sets the cached configuration for n points (the defaults when none is cached)."""
+    cfg = lookup(_arch(device), n, path)
+    set_tuning(*(cfg or (0, 0, 0, 0)))
     return get_tuning()
+
+
+def _label(cfg) -> str:
+    return "/".join(str(v) for v in cfg)
 
 
 def autotune(xyz, d: float, min_size: int = 1, max_size: int = 2**31 - 1,
              candidates=None, steps: int = 5, path: str | None = None, timer=None) -> dict:
-    """Times every candidate shape on ``xyz`` (a CUDA float32 [n, 3] tensor),
-    checks that all give the same labels, caches and applies the fastest.
+    """Times candidate configurations on ``xyz`` (a CUDA float32 [n, 3]
+    tensor), checks that all give the same labels, caches and applies the
+    fastest.
 
-    Returns {"best": (cell_blocks, stream_blocks), "ms": {shape: ms}}.
-    ``timer(fn, steps)`` may replace the wall-clock timing (for tests).
+    ``candidates``: explicit configurations (tuples of up to four knobs,
+    missing ones at their defaults), all timed; None: the coordinate search.
+    Returns {"best": four knobs, "ms": {"c/s/r/h": ms}}.  ``timer(fn, steps)``
+    may replace the wall-clock timing (for tests).
     """
     import torch
 
-    cands = list(candidates or CANDIDATES)
     n = int(xyz.shape[0])
     dev = xyz.device
     ws = new_workspace(n, dev)
@@ -118,20 +148,39 @@ def autotune(xyz, d: float, min_size: int = 1, max_size: int = 2**31 - 1,
     timer = timer or wall
     saved = get_tuning()
     times = {}
-    ref = None
+    ref = [None]
+
+    def measure(cfg):
+        cfg = _full(cfg)
+        if cfg in times:
+            return times[cfg]
+        set_tuning(*cfg)
+        times[cfg] = timer(call, steps)
+        torch.cuda.synchronize()
+        got = labels.clone()
+        if ref[0] is None:
+            ref[0] = got
+        elif not torch.equal(ref[0], got):
+            raise RuntimeError("labels depend on the launch configuration %s" % (cfg,))
+        return times[cfg]
+
     try:
-        for shape in cands:
-            set_tuning(*shape)
-            times[tuple(shape)] = timer(call, steps)
-            torch.cuda.synchronize()
-            got = labels.clone()
-            if ref is None:
-                ref = got
-            elif not torch.equal(ref, got):
-                raise RuntimeError("labels depend on the launch shape %s" % (shape,))
+        if candidates is not None:
+            for cfg in candidates:
+                measure(cfg)
+            best = min(times, key=times.get)
+        else:
+            best = DEFAULT
+            measure(best)
+            for knob in SEARCH_ORDER:
+                i = KNOBS.index(knob)
+                for v in VALUES[knob]:
+                    cfg = best[:i] + (v,) + best[i + 1:]
+                    measure(cfg)
+                best = min((c for c in times if all(c[j] == best[j] for j in range(4) if j != i)),
+                           key=times.get)
     finally:
         set_tuning(*saved)
-    best = min(times, key=times.get)
     record(_arch(dev), n, best, times[best], path)
     set_tuning(*best)
-    return {"best": best, "ms": {"%d/%d" % k: v for k, v in times.items()}}
+    return {"best": best, "ms": {_label(k): v for k, v in times.items()}}
