@@ -436,6 +436,7 @@ __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ parti
     P->bz = bits_for(NZ);
     P->giant = -1;
     P->nwork = 0;
+    P->ndefer[0] = P->ndefer[1] = 0;
     P->dense_cols = ((double)NX * (double)P->NYp <= (double)colgrid_cap) ? 1 : 0;
     P->hashed_cols = 0;
     uint64_t hcap = 1;
@@ -1392,6 +1393,18 @@ __device__ __forceinline__ bool any_joined(const float4 *__restrict__ spts, uint
     return false;
 }
 
+// A queued cell pair (A << 32 | B): joined unless already in one component,
+// tested point pair by point pair.
+__device__ __forceinline__ void defer_test(uint64_t e, const float4 *__restrict__ spts,
+                                           const uint32_t *__restrict__ cell_start,
+                                           int32_t *cpar, float d2) {
+    const int32_t A = (int32_t)(e >> 32), B = (int32_t)(e & 0xFFFFFFFFu);
+    const int32_t ra = uf_find(cpar, A), rb = uf_find(cpar, B);
+    if (ra == rb) return;
+    if (any_joined(spts, cell_start[A], cell_start[A + 1], cell_start[B], cell_start[B + 1], d2))
+        uf_link(cpar, ra, rb);
+}
+
 // Runs: cell B = A + 1 (the next cell in key order) is often A's neighbour
 // one step up in z, or one step along y in the next column.  Such a pair is
 // tested; each cell that is not joined to its predecessor this way starts a
@@ -1602,6 +1615,53 @@ constexpr int kNearGroup = 4;
 // candidate column (see k_hook_far's kFarSplitBelow).
 constexpr int64_t kNearSplitBelow = 131072;
 
+// Queued cell pairs a block of a hooking kernel holds before its flush.
+constexpr uint32_t kDeferBuf = 1024;
+
+// Cell pairs whose first points are not joined are queued in LDS, then in a
+// global queue, and tested by a later kernel, once the shell's other joins
+// are in: most of them then share a root and need no test.  A pair the
+// block's buffer cannot take is tested where it is found.
+struct DeferLds {
+    uint64_t buf[kDeferBuf];  // A << 32 | B
+    uint32_t n, gbase;
+};
+
+__device__ __forceinline__ bool defer_push(DeferLds &q, int32_t A, uint32_t B) {
+    const uint32_t slot = atomicAdd(&q.n, 1u);
+    if (slot >= kDeferBuf) return false;
+    q.buf[slot] = ((uint64_t)(uint32_t)A << 32) | B;
+    return true;
+}
+
+// After the block's last cell: its pairs go to the global queue (counter
+// *count) as far as the queue has room; the rest are tested here.
+template <int BLK>
+__device__ __forceinline__ void defer_flush(DeferLds &q, uint32_t *count,
+                                            uint64_t *__restrict__ defer, uint64_t cap,
+                                            const float4 *__restrict__ spts,
+                                            const uint32_t *__restrict__ cell_start,
+                                            int32_t *cpar, const Frame *__restrict__ frames,
+                                            const uint32_t *__restrict__ cell_frame, bool batched,
+                                            float d2_one) {
+    __syncthreads();
+    const uint32_t cnt = q.n < kDeferBuf ? q.n : kDeferBuf;
+    if (threadIdx.x == 0) q.gbase = cnt ? atomicAdd(count, cnt) : 0u;
+    __syncthreads();
+    const uint64_t gbase = q.gbase;
+    const uint32_t fit =
+        gbase >= cap ? 0u : (gbase + cnt <= cap ? cnt : (uint32_t)(cap - gbase));
+    for (uint32_t j = threadIdx.x; j < cnt; j += BLK) {
+        if (j < fit) {
+            defer[gbase + j] = q.buf[j];
+        } else {
+            const int32_t A = (int32_t)(q.buf[j] >> 32);
+            defer_test(q.buf[j], spts, cell_start, cpar,
+                       batched ? frames[cell_frame[A]].d2 : d2_one);
+        }
+    }
+}
+
 template <bool kSplit, int BLK>
 __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ spts,
                                                       const uint32_t *__restrict__ cell_start,
@@ -1612,7 +1672,9 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
                                                       const uint32_t *__restrict__ colbits,
                                                       const Frame *__restrict__ frames,
                                                       const uint32_t *__restrict__ cell_frame,
-                                                      int32_t *cpar, const Params *__restrict__ P) {
+                                                      int32_t *cpar, Params *__restrict__ P,
+                                                      uint64_t *__restrict__ defer,
+                                                      uint64_t defer_cap) {
     if (P->status != kStatusOk) return;
     const int64_t M = P->M;
     const ColIndex ci = colindex_of(P, colgrid, colbits, col_key, col_cell);
@@ -1627,6 +1689,11 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
     constexpr int kCand = kNG * kNearK;
     static_assert(kC % kNG == 0 && kCand <= 32, "groups cover the columns; 32-bit masks");
     if ((M < kNearSplitBelow) != kSplit) return;  // the other instance's case
+    // pairs whose first points are not joined: queued (see DeferLds)
+    __shared__ DeferLds dq;
+    if (threadIdx.x == 0) dq.n = 0;
+    __syncthreads();
+    auto queue = [&](int32_t A, uint32_t B) { return defer_push(dq, A, B); };
     // kSplit: one task per (cell, group); every task loads the cell's own data
     constexpr int kTasks = kSplit ? kGroups : 1;
     for (int64_t t = xcd_block<kXcdRunNear>() * BLK + threadIdx.x; t < M * kTasks;
@@ -1720,7 +1787,9 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
                 if (r == ra) continue;
                 FEC_COUNT(P, 1, 1);
                 FEC_COUNT(P, 3, (eA - sA) * (eb[i] - sb[i]));
-                if (((quick >> i) & 1u) || any_joined(spts, sA, eA, sb[i], eb[i], d2)) {
+                if (((quick >> i) & 1u) ||
+                    (!queue(A, fc[i / kNearK] + (uint32_t)(i % kNearK)) &&
+                     any_joined(spts, sA, eA, sb[i], eb[i], d2))) {
                     FEC_COUNT(P, 2, 1);
                     ra = uf_link_roots(cpar, uf_find(cpar, ra), r);
                 }
@@ -1751,12 +1820,37 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
                         if (dz < -1) continue;
                         const int32_t r = uf_find(cpar, (int32_t)B);
                         if (r == ra) continue;
-                        if (any_joined(spts, sA, eA, cell_start[B], cell_start[B + 1], d2))
+                        const uint32_t sB = cell_start[B];
+                        if (joined(pa.x, pa.y, pa.z, spts[sB], d2) ||
+                            (!queue(A, B) && any_joined(spts, sA, eA, sB, cell_start[B + 1], d2)))
                             ra = uf_link(cpar, ra, r);
                     }
                 }
             }
         }
+    }
+    defer_flush<BLK>(dq, &P->ndefer[0], defer, defer_cap, spts, cell_start, cpar, frames,
+                     cell_frame, batched, d2_one);
+}
+
+// The pairs a hooking kernel queued (the first min(count, capacity) entries
+// of the queue; `which` 0: near shell, 1: far shell).
+__global__ __launch_bounds__(kBlock) void k_deferred(const float4 *__restrict__ spts,
+                                                     const uint32_t *__restrict__ cell_start,
+                                                     const Frame *__restrict__ frames,
+                                                     const uint32_t *__restrict__ cell_frame,
+                                                     int32_t *cpar, const Params *__restrict__ P,
+                                                     const uint64_t *__restrict__ defer,
+                                                     uint64_t defer_cap, int which) {
+    if (P->status != kStatusOk) return;
+    const uint64_t cnt = P->ndefer[which] < defer_cap ? P->ndefer[which] : defer_cap;
+    const bool batched = P->nframes > 1;
+    const float d2_one = P->d2;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < cnt;
+         i += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t e = defer[i];
+        const int32_t A = (int32_t)(e >> 32);
+        defer_test(e, spts, cell_start, cpar, batched ? frames[cell_frame[A]].d2 : d2_one);
     }
 }
 
@@ -1940,7 +2034,9 @@ __global__ __launch_bounds__(BLK) void k_hook_far(const float4 *__restrict__ spt
                                                       const uint32_t *__restrict__ work,
                                                       const Frame *__restrict__ frames,
                                                       const uint32_t *__restrict__ cell_frame,
-                                                      int32_t *cpar, const Params *__restrict__ P) {
+                                                      int32_t *cpar, Params *__restrict__ P,
+                                                      uint64_t *__restrict__ defer,
+                                                      uint64_t defer_cap) {
     if (P->status != kStatusOk) return;
     const int64_t M = P->M;
     const uint32_t nwork = P->nwork;
@@ -1960,6 +2056,10 @@ __global__ __launch_bounds__(BLK) void k_hook_far(const float4 *__restrict__ spt
     static_assert(kG * kK <= 32, "candidate masks are 32-bit");
     static_assert(kG <= 32 && 24 % kG == 0, "groups cover the 24 columns");
     if ((nwork < kFarSplitBelow) != kSplit) return;  // the other instance's case
+    // pairs whose first points are not joined: queued (see DeferLds)
+    __shared__ DeferLds dq;
+    if (threadIdx.x == 0) dq.n = 0;
+    __syncthreads();
     // kSplit: one task per (work cell, group of kG columns).  The groups of a
     // cell are independent; a lane that walks all of them in turn carries
     // one long chain of dependent loads (about 50 us per cell, measured).
@@ -1979,6 +2079,7 @@ __global__ __launch_bounds__(BLK) void k_hook_far(const float4 *__restrict__ spt
         const uint32_t sA = cell_start[A], eA = cell_start[A + 1];
         int32_t ra = uf_find(cpar, A);
         const float d2 = batched ? frames[cell_frame[A]].d2 : d2_one;
+        const float4 pa = spts[sA];  // A's first point, for the one-pair tests
         auto pair = [&](uint32_t B, int32_t rb) {
             FEC_COUNT(P, 5, 1);
             if (rb == ra) return;
@@ -1986,7 +2087,9 @@ __global__ __launch_bounds__(BLK) void k_hook_far(const float4 *__restrict__ spt
             if (rb == ra) return;
             FEC_COUNT(P, 6, 1);
             FEC_COUNT(P, 7, (eA - sA) * (cell_start[B + 1] - cell_start[B]));
-            if (any_joined(spts, sA, eA, cell_start[B], cell_start[B + 1], d2))
+            const uint32_t sB = cell_start[B];
+            if (joined(pa.x, pa.y, pa.z, spts[sB], d2) ||
+                (!defer_push(dq, A, B) && any_joined(spts, sA, eA, sB, cell_start[B + 1], d2)))
                 ra = uf_link_roots(cpar, uf_find(cpar, ra), rb);
         };
         // own column (first task of the cell): the cells two steps down (if
@@ -2088,6 +2191,8 @@ __global__ __launch_bounds__(BLK) void k_hook_far(const float4 *__restrict__ spt
             }
         }
     }
+    defer_flush<BLK>(dq, &P->ndefer[1], defer, defer_cap, spts, cell_start, cpar, frames,
+                     cell_frame, batched, d2_one);
 }
 
 // ------------------------------------------------------------- 9. finalize
@@ -2347,8 +2452,8 @@ const char *stage_name(int s) {
     static const char *names[kNumStages] = {
         "bbox",       "plan",      "keys",       "sort_hist",   "sort_scan",    "sort_scatter",
         "gather",     "tile_scan", "cells",      "colgrid",     "runs",         "hook_near",
-        "compress_1", "giant",     "work_list",  "hook_far",    "compress_2",   "final_cells",
-        "final_labels", "finish"};
+        "deferred",   "compress_1", "giant",     "work_list",  "hook_far",    "compress_2",
+        "final_cells", "final_labels", "finish"};
     return (s >= 0 && s < kNumStages) ? names[s] : "";
 }
 
@@ -2415,6 +2520,7 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     int32_t *blkhead = reinterpret_cast<int32_t *>(w + L.blkhead);
     uint64_t *gbits = reinterpret_cast<uint64_t *>(w + L.gbits);
     uint32_t *work = reinterpret_cast<uint32_t *>(w + L.work);
+    uint64_t *defer = reinterpret_cast<uint64_t *>(w + L.defer);
     uint32_t *cell_frame = nframes > 1 ? reinterpret_cast<uint32_t *>(w + L.cell_frame) : nullptr;
 
     const int64_t ntiles = L.ntiles;
@@ -2489,11 +2595,12 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
 #define FEC_HOOK_NEAR(SPLIT, BLK)                                                          \
     FEC_LAUNCH(kStHookNear, k_hook_near<SPLIT, BLK><<<nb_cells, BLK, 0, st>>>(               \
                                 spts, cell_start, cell_key, col_key, col_cell, colgrid,      \
-                                colbits, frames, cell_frame, cpar, P))
+                                colbits, frames, cell_frame, cpar, P, defer, L.defer_cap))
 #define FEC_HOOK_FAR(SPLIT, BLK)                                                           \
     FEC_LAUNCH(kStHookFar, k_hook_far<SPLIT, BLK><<<nb_cells, BLK, 0, st>>>(                 \
                                spts, cell_start, cell_key, col_key, col_cell, colgrid,       \
-                               colbits, gbits, work, frames, cell_frame, cpar, P))
+                               colbits, gbits, work, frames, cell_frame, cpar, P, defer,     \
+                               L.defer_cap))
     if (n >= kNearSplitBelow) {
         if (hook_block == 64) FEC_HOOK_NEAR(false, 64);
         else if (hook_block == 128) FEC_HOOK_NEAR(false, 128);
@@ -2502,6 +2609,9 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     if (hook_block == 64) FEC_HOOK_NEAR(true, 64);
     else if (hook_block == 128) FEC_HOOK_NEAR(true, 128);
     else FEC_HOOK_NEAR(true, 256);
+    FEC_LAUNCH(kStDeferred, k_deferred<<<nb_cells, kBlock, 0, st>>>(
+                                spts, cell_start, frames, cell_frame, cpar, P, defer,
+                                L.defer_cap, 0));
     FEC_LAUNCH(kStCompress1, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P));
     FEC_LAUNCH(kStGiant, k_giant<<<(unsigned)nframes, 1024, 0, st>>>(cpar, frames, P));
     FEC_LAUNCH(kStWorkList, k_nongiant<<<nb_cells, kBlock, 0, st>>>(cpar, gbits, work, frames,
@@ -2516,6 +2626,9 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     else FEC_HOOK_FAR(true, 256);
 #undef FEC_HOOK_NEAR
 #undef FEC_HOOK_FAR
+    FEC_LAUNCH(kStDeferred, k_deferred<<<nb_cells, kBlock, 0, st>>>(
+                                spts, cell_start, frames, cell_frame, cpar, P, defer,
+                                L.defer_cap, 1));
     FEC_LAUNCH(kStCompress2, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P));
     FEC_LAUNCH(kStFinalCells, k_final_cells<<<nb_cells, kBlock, 0, st>>>(
                                   cpar, cell_start, sorig, csize, ccanon, P));

@@ -86,6 +86,9 @@ struct Params {
     int32_t giant;        // root of the largest component after sampling (-1: none)
     uint32_t nwork;       // cells outside that component (full-stencil work list)
     uint32_t pad1;
+    // Cell pairs whose first points are not joined, queued by the near and
+    // the far shell for a full test once the shell's other joins are in.
+    uint32_t ndefer[2];
     int32_t kept;         // kept clusters
     int32_t max_cell;     // largest number of points in one cell
     // Hashed column index (when the dense one does not fit): open addressing
@@ -103,7 +106,8 @@ struct Layout {
     size_t params, frames, partials, tile_cnt, tile_off;
     size_t keys0, keys1, vals0, vals1, th, dtot;
     size_t spts, sorig, cell_start, cell_key, cpar, csize, ccanon;
-    size_t col_key, col_cell, colgrid, colbits, heads, blkhead, gbits, work, cell_frame;
+    size_t col_key, col_cell, colgrid, colbits, heads, blkhead, gbits, work, cell_frame, defer;
+    uint64_t defer_cap;  // entries of the deferred-pair queue
     uint64_t colgrid_cap;
     size_t total;
     int64_t ntiles;
@@ -169,6 +173,8 @@ constexpr Layout make_layout(int64_t n, int32_t nframes = 1) {
     L.blkhead = take((size_t)L.ntiles * sizeof(int32_t));
     L.gbits = take((un / 64 + 1) * sizeof(uint64_t));
     L.work = take(un * sizeof(uint32_t));
+    L.defer_cap = un / 2 + 1024;
+    L.defer = take((size_t)L.defer_cap * sizeof(uint64_t));
     L.cell_frame = take(nframes > 1 ? un * sizeof(uint32_t) : 0);  // frame of every cell
     L.total = off;
     return L;
@@ -188,6 +194,7 @@ enum Stage : int {
     kStColGrid,
     kStRuns,
     kStHookNear,
+    kStDeferred,
     kStCompress1,
     kStGiant,
     kStWorkList,
