@@ -209,6 +209,16 @@ int32_t fec_server_submit(fec_server *server, const float *xyz, int64_t n, float
 int32_t fec_server_pump(fec_server *server, int32_t wait);
 
 /*
+ * fec_server_pump without waiting, then, when it completed nothing, watches
+ * the batches in flight for up to max_wait_us microseconds and retires the
+ * first that finishes (launching queued requests into the slots it frees).
+ * A caller that must also admit new requests at known times passes the time
+ * left until the next one.  Returns the number of requests completed, or a
+ * negative status (FEC_EINVAL for max_wait_us < 0).
+ */
+int32_t fec_server_pump_for(fec_server *server, int64_t max_wait_us);
+
+/*
  * Takes up to max completed requests, oldest first: ticket, k (kept
  * clusters, or a negative FEC_* status) and latency in milliseconds from
  * submission to retirement by fec_server_pump.  Returns the number taken.

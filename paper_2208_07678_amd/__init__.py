@@ -72,6 +72,7 @@ def _load():
         "fec_server_slot_points": ([vp], i64),
         "fec_server_submit": ([vp, vp, i64, f32, i32, i32, vp, vp], i32),
         "fec_server_pump": ([vp, i32], i32),
+        "fec_server_pump_for": ([vp, i64], i32),
         "fec_server_poll": ([vp, vp, vp, vp, i32], i32),
         "fec_server_stats": ([vp, vp, i32], i32),
         "fec_server_destroy": ([vp], None),
@@ -99,6 +100,7 @@ EXPORTED = [
     "fec_set_stream", "fec_release",
     "fec_cluster_batch_async", "fec_batch_workspace_bytes", "fec_server_slot_bytes",
     "fec_server_create", "fec_server_slot_points", "fec_server_submit", "fec_server_pump",
+    "fec_server_pump_for",
     "fec_server_poll", "fec_server_stats", "fec_server_destroy", "fec_tuning_set",
     "fec_tuning_get",
     "fec_last_error", "fec_version", "fec_workspace_stats", "fec_profile_enable",
@@ -408,6 +410,14 @@ class Server:
         rc = _load().fec_server_pump(self._h, 1 if wait else 0)
         if rc < 0:
             raise FecError(rc, "fec_server_pump failed")
+        return rc
+
+    def pump_for(self, max_wait_us: int) -> int:
+        """pump(); when nothing completed, watch the batches in flight for up
+        to max_wait_us microseconds and retire the first that finishes."""
+        rc = _load().fec_server_pump_for(self._h, max(0, int(max_wait_us)))
+        if rc < 0:
+            raise FecError(rc, "fec_server_pump_for failed")
         return rc
 
     def poll(self, max_items: int = 4096):

@@ -448,6 +448,36 @@ int32_t fec_server_pump(fec_server *S, int32_t wait) {
     return completed;
 }
 
+int32_t fec_server_pump_for(fec_server *S, int64_t max_wait_us) {
+    if (!S || max_wait_us < 0) return FEC_EINVAL;
+    int32_t completed = fec_server_pump(S, 0);
+    if (completed != 0 || max_wait_us == 0) return completed;
+    // spin on the events of the batches in flight (a completion is seen
+    // within one event query, not one sleep of the caller)
+    const auto until = Clock::now() + std::chrono::microseconds(max_wait_us);
+    bool busy = true;
+    while (busy && Clock::now() < until) {
+        busy = false;
+        for (auto &s : S->slots) {
+            if (!s.busy) continue;
+            busy = true;
+            const int32_t c = retire(S, s, false);
+            if (c < 0) return c;
+            completed += c;
+        }
+        if (completed) break;
+    }
+    if (completed) {  // refill the slots just freed
+        for (auto &s : S->slots) {
+            if (S->queue.empty()) break;
+            if (s.busy) continue;
+            const int32_t f = launch(S, s);
+            if (f < 0) return f;
+        }
+    }
+    return completed;
+}
+
 int32_t fec_server_poll(fec_server *S, int64_t *tickets, int32_t *k, double *latency_ms,
                         int32_t max) {
     if (!S || max < 0) return FEC_EINVAL;

@@ -121,6 +121,34 @@ def test_arrivals_while_batches_run():
     srv.close()
 
 
+def test_pump_for_retires_as_batches_finish():
+    # a client that admits requests at known times waits with pump_for:
+    # every request completes, with the labels of its single call
+    import torch
+    frames = [synth.lidar_frame(n=8000 + 3000 * i, seed=90 + i) for i in range(6)]
+    ts = [torch.from_numpy(f).to("cuda:0") for f in frames]
+    srv = _server(budget_mb=256, nslots=2, frames=4)
+    results = {}
+    for i, t in enumerate(ts):
+        srv.submit(t, 0.35, 20, 10**9)
+        srv.pump()
+        srv.pump_for(200)
+        for tk, lab, k, _ in srv.poll():
+            results[tk] = (lab, k)
+    for _ in range(10000):
+        if len(results) == len(ts):
+            break
+        srv.pump_for(1000)
+        for tk, lab, k, _ in srv.poll():
+            results[tk] = (lab, k)
+    assert len(results) == len(ts)
+    for i, f in enumerate(frames):
+        want, wk = oracle.fec(f, 0.35, 20, 10**9)
+        lab, k = results[i]
+        assert np.array_equal(lab.cpu().numpy(), want) and k == wk, i
+    srv.close()
+
+
 def test_admission_limits_and_argument_checks():
     import torch
 
