@@ -595,7 +595,11 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(const uint64_t *__restrict
     const int tid = threadIdx.x, wave = tid >> 6, lane = __lane_id();
     for (int i = tid; i < (kBlock / 64) * R; i += kBlock) (&s_cnt[0][0])[i] = 0;
     __syncthreads();
-    const int64_t tile = blockIdx.x;
+    // tiles by XCD eighths: neighbouring tiles write neighbouring words of
+    // each digit's row of counts, which their XCD's L2 then merges into
+    // whole lines (4-byte writes from tiles on different XCDs would each
+    // cost a partial line in memory)
+    const int64_t tile = xcd_block_eighths();
     const int shift = P->key_shift + pass * RB;
     const int64_t base = tile * kTile + (int64_t)wave * (64 * kItems);
     uint64_t v[kItems];
@@ -688,7 +692,19 @@ k_sort_scatter(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
     __shared__ uint32_t s_tmp[kBlock / 64];
     const int tid = threadIdx.x, wave = tid >> 6, lane = __lane_id();
     for (int i = tid; i < (kBlock / 64) * R; i += kBlock) (&s_cnt[0][0])[i] = 0;
-    const int64_t tile = blockIdx.x;
+    // tiles by XCD eighths: neighbouring tiles read neighbouring words of
+    // each digit's row of tile positions through one L2
+    const int64_t tile = xcd_block_eighths();
+    // the tile's words first: their loads overlap the digit bases below
+    const int shift = P->key_shift + pass * RB;
+    const bool pair = P->pair_mode != 0;
+    const int64_t base = tile * kTile + (int64_t)wave * (64 * kItems);
+    uint64_t v[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int64_t e = base + k * 64 + lane;
+        v[k] = e < n ? src[e] : 0ull;
+    }
     {
         // this tile's position within each digit, plus the digit's base (the
         // totals of all smaller digits); thread t owns digits t*DPT ..
@@ -702,17 +718,7 @@ k_sort_scatter(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
             s_base[tid * DPT + q] = tv[q] + th[(int64_t)(tid * DPT + q) * ntiles + tile];
     }
     __syncthreads();
-    const int shift = P->key_shift + pass * RB;
-    const bool pair = P->pair_mode != 0;
-    const int64_t base = tile * kTile + (int64_t)wave * (64 * kItems);
-
-    uint64_t v[kItems];
     uint32_t rk[kItems];
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        const int64_t e = base + k * 64 + lane;
-        v[k] = e < n ? src[e] : 0ull;
-    }
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const bool valid = base + k * 64 + lane < n;
