@@ -765,7 +765,7 @@ def main():
                    "mean_points_per_cell": n / max(stats.get("cells") or 1, 1),
                    "radix_passes": stats.get("radix_passes"),
                    "work_cells": stats.get("work_cells"),
-                   "launch_config": dict(zip(("cell_blocks", "stream_blocks", "radix_bits", "hook_block"), fec.get_tuning())),
+                   "launch_config": dict(zip(("cell_blocks", "stream_blocks", "radix_bits", "hook_block", "near_sampling"), fec.get_tuning())),
                    "autotuned": tuned is not None},
         "roofline": roofline,
         "call_ms": call_ms,

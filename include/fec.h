@@ -260,11 +260,14 @@ const char *fec_version(void);
  * out[11] cells left outside the largest component after the near shell,
  * out[12] that component's root cell, out[13..20] diagnostic event counts
  * (zero unless the library was built with FEC_COUNTERS defined), out[21]
- * the column index used (0 binary search, 1 dense table, 2 hash table).
+ * the column index used (0 binary search, 1 dense table, 2 hash table),
+ * out[22] cells left outside the largest component after the sampling links
+ * (the cells the near shell visits; 0 when the cloud has fewer than 131,072
+ * cells, where the near shell visits every cell).
  * For a batched call the grid fields describe the frames' stacked grid,
- * out[11] counts the cells outside each frame's largest component and
- * out[12] is -1.
- * Writes min(max_out, 22) values; returns that count or a negative status.
+ * out[11] and out[22] count the cells outside each frame's largest component
+ * and out[12] is -1.
+ * Writes min(max_out, 23) values; returns that count or a negative status.
  */
 int32_t fec_workspace_stats(const void *workspace, void *stream, int64_t *out, int32_t max_out);
 
@@ -291,14 +294,19 @@ int32_t fec_stage_count(void);
  *   radix_bits     bits per radix-sort pass: 8, 9, 10 or 11 (default 9);
  *                  wider digits take fewer passes over larger tables;
  *   hook_block     threads per block of the hooking kernels: 64, 128 or
- *                  256 (default 256).
+ *                  256 (default 256);
+ *   near_sampling  whether clouds of at least 131,072 cells first link each
+ *                  cell to the first cells of its dx = +1 neighbour columns
+ *                  and run the near shell only outside the largest component
+ *                  so formed: 0 when the cloud has at least 2^23 points
+ *                  (default), 1 always, 2 never.
  * 0 restores a knob's default.  Labels and counts do not depend on any of
  * them.  Returns FEC_OK, or FEC_EINVAL for a value outside its set.
  */
 int32_t fec_tuning_set(int32_t cell_blocks, int32_t stream_blocks, int32_t radix_bits,
-                       int32_t hook_block);
+                       int32_t hook_block, int32_t near_sampling);
 int32_t fec_tuning_get(int32_t *cell_blocks, int32_t *stream_blocks, int32_t *radix_bits,
-                       int32_t *hook_block);
+                       int32_t *hook_block, int32_t *near_sampling);
 const char *fec_stage_name(int32_t stage);
 
 #ifdef __cplusplus

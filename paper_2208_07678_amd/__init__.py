@@ -66,8 +66,8 @@ def _load():
                                      vp], i32),
         "fec_batch_workspace_bytes": ([i64, i32], ctypes.c_size_t),
         "fec_server_slot_bytes": ([i64, i32], ctypes.c_size_t),
-        "fec_tuning_set": ([i32, i32, i32, i32], i32),
-        "fec_tuning_get": ([vp, vp, vp, vp], i32),
+        "fec_tuning_set": ([i32, i32, i32, i32, i32], i32),
+        "fec_tuning_get": ([vp, vp, vp, vp, vp], i32),
         "fec_server_create": ([ctypes.c_size_t, i32, i32, vp], i32),
         "fec_server_slot_points": ([vp], i64),
         "fec_server_submit": ([vp, vp, i64, f32, i32, i32, vp, vp], i32),
@@ -110,7 +110,7 @@ EXPORTED = [
 STATS_FIELDS = ["n", "finite_points", "cells", "columns", "key_bits", "radix_passes",
                 "grid_x", "grid_y", "grid_z", "max_points_per_cell", "status",
                 "work_cells", "giant_root"] + ["counter%d" % i for i in range(8)] + [
-                "column_index"]
+                "column_index", "near_work_cells"]
 
 
 class FecError(RuntimeError):
@@ -233,19 +233,20 @@ def cluster_noalloc(xyz, d: float, min_size: int = 1, max_size: int = 2**31 - 1,
 
 
 def set_tuning(cell_blocks: int = 0, stream_blocks: int = 0, radix_bits: int = 0,
-               hook_block: int = 0) -> None:
+               hook_block: int = 0, near_sampling: int = 0) -> None:
     """Launch configuration of later calls (0 = a knob's default): grid sizes
     of the per-cell and streaming kernels, radix-sort digit width, block size
-    of the hooking kernels; see ``paper_2208_07678_amd.tune``."""
+    of the hooking kernels, sampling links before the near shell (0 by cloud
+    size, 1 on, 2 off); see ``paper_2208_07678_amd.tune``."""
     rc = _load().fec_tuning_set(int(cell_blocks), int(stream_blocks), int(radix_bits),
-                                int(hook_block))
+                                int(hook_block), int(near_sampling))
     if rc != FEC_OK:
         _raise(rc)
 
 
-def get_tuning() -> tuple[int, int, int, int]:
-    """(cell_blocks, stream_blocks, radix_bits, hook_block) in force."""
-    v = [ctypes.c_int32() for _ in range(4)]
+def get_tuning() -> tuple[int, int, int, int, int]:
+    """(cell_blocks, stream_blocks, radix_bits, hook_block, near_sampling) in force."""
+    v = [ctypes.c_int32() for _ in range(5)]
     _load().fec_tuning_get(*[ctypes.byref(x) for x in v])
     return tuple(int(x.value) for x in v)
 

@@ -337,14 +337,14 @@ int32_t fec_workspace_stats(const void *workspace, void *stream, int64_t *out, i
     if (hipMemcpyAsync(&P, workspace, sizeof P, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return fail(FEC_EDEVICE, "reading the workspace failed");
-    const int64_t v[22] = {P.n,  P.nvalid, P.M,  P.Mcol,     P.key_bits, P.npasses, P.NX,
+    const int64_t v[23] = {P.n,  P.nvalid, P.M,  P.Mcol,     P.key_bits, P.npasses, P.NX,
                            P.NY, P.NZ,     P.max_cell, P.status, P.nwork,   P.giant,
                            (int64_t)P.counters[0], (int64_t)P.counters[1],
                            (int64_t)P.counters[2], (int64_t)P.counters[3],
                            (int64_t)P.counters[4], (int64_t)P.counters[5],
                            (int64_t)P.counters[6], (int64_t)P.counters[7],
-                           P.dense_cols ? 1 : (P.hashed_cols ? 2 : 0)};
-    const int32_t c = max_out < 22 ? max_out : 22;
+                           P.dense_cols ? 1 : (P.hashed_cols ? 2 : 0), P.nwork0};
+    const int32_t c = max_out < 23 ? max_out : 23;
     for (int32_t i = 0; i < c; ++i) out[i] = v[i];
     ok();
     return c;
@@ -376,7 +376,7 @@ void fec_profile_reset(void) {
 }
 
 int32_t fec_tuning_set(int32_t cell_blocks, int32_t stream_blocks, int32_t radix_bits,
-                       int32_t hook_block) {
+                       int32_t hook_block, int32_t near_sampling) {
     if (cell_blocks < 0 || stream_blocks < 0 || cell_blocks > (1 << 20) ||
         stream_blocks > (1 << 20))
         return fail(FEC_EINVAL, "block counts outside [0, 2^20]");
@@ -384,20 +384,23 @@ int32_t fec_tuning_set(int32_t cell_blocks, int32_t stream_blocks, int32_t radix
         return fail(FEC_EINVAL, "radix_bits=%d not in {0, 8, 9, 10, 11}", radix_bits);
     if (hook_block != 0 && hook_block != 64 && hook_block != 128 && hook_block != 256)
         return fail(FEC_EINVAL, "hook_block=%d not in {0, 64, 128, 256}", hook_block);
+    if (near_sampling < 0 || near_sampling > 2)
+        return fail(FEC_EINVAL, "near_sampling=%d not in {0, 1, 2}", near_sampling);
     fec::set_tuning({cell_blocks ? cell_blocks : fec::kDefaultCellBlocks,
                      stream_blocks ? stream_blocks : fec::kDefaultStreamBlocks,
                      radix_bits ? radix_bits : fec::kDefaultRadixBits,
-                     hook_block ? hook_block : fec::kDefaultHookBlock});
+                     hook_block ? hook_block : fec::kDefaultHookBlock, near_sampling});
     return ok();
 }
 
 int32_t fec_tuning_get(int32_t *cell_blocks, int32_t *stream_blocks, int32_t *radix_bits,
-                       int32_t *hook_block) {
+                       int32_t *hook_block, int32_t *near_sampling) {
     const fec::Tuning t = fec::tuning();
     if (cell_blocks) *cell_blocks = t.cell_blocks;
     if (stream_blocks) *stream_blocks = t.stream_blocks;
     if (radix_bits) *radix_bits = t.radix_bits;
     if (hook_block) *hook_block = t.hook_block;
+    if (near_sampling) *near_sampling = t.near_sampling;
     return ok();
 }
 

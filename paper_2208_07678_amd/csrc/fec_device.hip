@@ -6,8 +6,9 @@
 // point-wise loop is replaced by a grid-based design:
 //
 //   bbox -> plan -> keys -> radix sort passes -> gather -> cell table
-//   -> column index (dense table, hash or search) -> runs -> hook (near
-//   shell) -> compress -> giant component / work list -> hook (far shell)
+//   -> column index (dense table, hash or search) -> runs -> sampling links
+//   -> compress -> giant component / work list -> hook (near shell)
+//   -> compress -> giant component / work list -> hook (far shell)
 //   -> compress -> cluster sizes/ids -> labels
 //
 // One call covers one cloud or a batch of frames: every frame has its own
@@ -25,8 +26,10 @@
 // is joined, so a cell pair is tested point pair by point pair only until
 // the first joined pair, and not at all when both cells already share a
 // union-find root.  The near shell (offsets within 1) runs first; after a
-// compression most of a dense surface is one component and the far shell
-// (offsets of 2) is mostly skipped by the root comparison.
+// compression most of a dense surface is one component, and the far shell
+// (offsets of 2) visits only the cells outside it.  On large clouds the near
+// shell itself is preceded by one round of sampled links and runs only for
+// the cells outside the component these form.
 //
 // Determinism.  The union-find always hooks the root of higher rank under
 // the other (rank: a fixed scramble of the cell id); the partition it
@@ -436,6 +439,7 @@ __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ parti
     P->bz = bits_for(NZ);
     P->giant = -1;
     P->nwork = 0;
+    P->nwork0 = 0;
     P->ndefer[0] = P->ndefer[1] = 0;
     P->dense_cols = ((double)NX * (double)P->NYp <= (double)colgrid_cap) ? 1 : 0;
     P->hashed_cols = 0;
@@ -1591,9 +1595,20 @@ __device__ __forceinline__ void near_col(int q, int &dx, int &dy) {
     dy = q == 0 ? 1 : q - 2;
 }
 
-// Near shell over every cell: a cell pair is skipped when both cells
-// already share a root; otherwise point pairs are tested until the first
-// joined one, which joins the two components.
+// Near shell: a cell pair is skipped when both cells already share a root;
+// otherwise point pairs are tested until the first joined one, which joins
+// the two components.
+//
+// On large cell tables the shell runs in two steps, after the sampling
+// idea of Afforest (Sutton et al., 2018): first every cell links to the
+// first cell of each forward column when their first points are joined
+// (one round of loads, no further search), which joins most of the ground
+// into one component; that component is found (k_giant) and only the cells
+// outside it run the full near shell, on their forward pairs and on their
+// backward pairs towards the giant component.  A pair with both cells in
+// the giant component is already joined; any other pair has a cell outside
+// it, which handles the pair.  Small cell tables run the full shell on every
+// cell, one task per candidate column.
 //
 // The kernel is latency bound, so the loads of one cell are issued in a
 // few independent rounds rather than as one long dependent chain: (1) the
@@ -1606,19 +1621,14 @@ __device__ __forceinline__ void near_col(int q, int &dx, int &dy) {
 // column's cells within reach are located directly (column_seek) and tested
 // after.
 //
-// One cell per column (kNearK = 1) is fastest on the map and on batches of
-// frames, although more columns then take the second path: the kernel's
-// registers (94 against 115 with two cells and 139 with three) allow five
-// waves per SIMD instead of four or three, and the columns of these clouds
-// hold 1.5 cells on average, so most of the further loads were wasted.
-// Measured per call: map 2.08 -> 1.71 ms, 64-frame batch 0.45 -> 0.32 ms.
 constexpr int kNearK = 1;
 // Columns per group on large cell tables: all four (groups of two or one,
 // with fewer registers, measured slower on the map: 1.67 -> 1.76 / 1.97 ms).
 constexpr int kNearGroup = 4;
 
 // Cell tables shorter than this give each cell four tasks, one per
-// candidate column (see k_hook_far's kFarSplitBelow).
+// candidate column (see k_hook_far's kFarSplitBelow); longer ones take the
+// sampling links and the work list.
 constexpr int64_t kNearSplitBelow = 131072;
 
 // Queued cell pairs a block of a hooking kernel holds before its flush.
@@ -1668,7 +1678,33 @@ __device__ __forceinline__ void defer_flush(DeferLds &q, uint32_t *count,
     }
 }
 
-template <bool kSplit, int BLK>
+// Is cell B in the giant component of the last k_nongiant (bitmap)?
+__device__ __forceinline__ bool is_giant(const uint64_t *__restrict__ gbits, uint32_t B) {
+    return (gbits[B >> 6] >> (B & 63)) & 1ull;
+}
+
+// Forms of the near shell: every cell, one task per candidate column (small
+// cell tables); every cell, one task per cell (large tables); on large
+// tables of large clouds, the sampling links and then the full shell over
+// the cells outside their giant component.
+constexpr int kNearSplit = 0, kNearAll = 1, kNearSample = 2, kNearWork = 3;
+// The sampling links go to the first cells of the three columns at dx = +1
+// (mask over near_col's columns): the column (0, +1) adds few links the runs
+// have not made already (map: sampling 0.65 ms and near shell 0.55 ms either
+// way; only (1, 0): 0.57 and 0.71 ms).  Sampling from run starts only, or
+// with one compare-and-swap per link and no retry, leaves no giant component
+// (with no retry a root takes at most one hook, and the trees stay small).
+constexpr uint32_t kSampleCols = 0xEu;
+// Clouds of at least this many points take the sampling links (unless the
+// launch configuration says otherwise, see fec_tuning_set).  They pay
+// where the near shell's cells in the giant component are expensive, on
+// dense accumulated ground (27 M-point map: sampling, near shell, queued
+// pairs and compression 1.53 -> 1.43 ms, call 4.20 -> 4.06 ms); on single
+// scans the shell is cheap already and the sampling costs more than it
+// saves (64-frame batch of 5.4 M points: 0.40 -> 0.50 ms).
+constexpr int64_t kSampleMinPoints = 1 << 23;
+
+template <int kMode, int BLK>
 __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ spts,
                                                       const uint32_t *__restrict__ cell_start,
                                                       const uint64_t *__restrict__ cell_key,
@@ -1676,6 +1712,8 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
                                                       const uint32_t *__restrict__ col_cell,
                                                       const uint32_t *__restrict__ colgrid,
                                                       const uint32_t *__restrict__ colbits,
+                                                      const uint64_t *__restrict__ gbits,
+                                                      const uint32_t *__restrict__ work,
                                                       const Frame *__restrict__ frames,
                                                       const uint32_t *__restrict__ cell_frame,
                                                       int32_t *cpar, Params *__restrict__ P,
@@ -1683,28 +1721,38 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
                                                       uint64_t defer_cap) {
     if (P->status != kStatusOk) return;
     const int64_t M = P->M;
+    constexpr bool kSplit = kMode == kNearSplit;
+    constexpr bool kSample = kMode == kNearSample;
+    constexpr bool kWork = kMode == kNearWork;
+    if ((M < kNearSplitBelow) != kSplit) return;  // another form's case
     const ColIndex ci = colindex_of(P, colgrid, colbits, col_key, col_cell);
     const float d2_one = P->d2;
     const bool batched = P->nframes > 1;
     const Grid g = grid_of(P);
-    constexpr int kC = 4;
+    // columns: the four forward ones, and on the work list the four
+    // backward ones after them
+    constexpr int kC = kWork ? 8 : 4;
     // columns per group: a group's loads are issued together, the groups of
     // a cell one after the other (fewer registers, more waves)
     constexpr int kNG = kSplit ? 1 : kNearGroup;
     constexpr int kGroups = kC / kNG;
     constexpr int kCand = kNG * kNearK;
     static_assert(kC % kNG == 0 && kCand <= 32, "groups cover the columns; 32-bit masks");
-    if ((M < kNearSplitBelow) != kSplit) return;  // the other instance's case
-    // pairs whose first points are not joined: queued (see DeferLds)
+    // pairs whose first points are not joined: queued (see DeferLds); the
+    // sampling links test first points only
     __shared__ DeferLds dq;
-    if (threadIdx.x == 0) dq.n = 0;
-    __syncthreads();
+    if (!kSample) {
+        if (threadIdx.x == 0) dq.n = 0;
+        __syncthreads();
+    }
     auto queue = [&](int32_t A, uint32_t B) { return defer_push(dq, A, B); };
     // kSplit: one task per (cell, group); every task loads the cell's own data
     constexpr int kTasks = kSplit ? kGroups : 1;
-    for (int64_t t = xcd_block<kXcdRunNear>() * BLK + threadIdx.x; t < M * kTasks;
-         t += (int64_t)gridDim.x * BLK) {
-        const int32_t A = (int32_t)(t / kTasks);
+    const uint64_t ntask = kWork ? (uint64_t)P->nwork0 : (uint64_t)M * kTasks;
+    const uint64_t t0 = kWork ? (uint64_t)xcd_block<kXcdRunFar>() * BLK + threadIdx.x
+                              : (uint64_t)xcd_block<kXcdRunNear>() * BLK + threadIdx.x;
+    for (uint64_t t = t0; t < ntask; t += (uint64_t)gridDim.x * BLK) {
+        const int32_t A = kWork ? (int32_t)work[t] : (int32_t)(t / kTasks);
         const int task = (int)(t % kTasks);
         // round 1
         const uint64_t key = cell_key[A];
@@ -1722,6 +1770,9 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
 #pragma unroll 1
         for (int grp = kSplit ? task : 0; grp < (kSplit ? task + 1 : kGroups); ++grp) {
             const int o0 = grp * kNG;
+            // backward columns (work list): only pairs towards the giant
+            // component, the others are their other cell's forward pairs
+            const bool back = kWork && o0 >= 4;
             // round 2: neighbour columns
             bool has[kNG];
             uint32_t fc[kNG];
@@ -1730,10 +1781,15 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
 #pragma unroll
             for (int o = 0; o < kNG; ++o) {
                 int dx, dy;
-                near_col(o0 + o, dx, dy);
+                near_col((o0 + o) & 3, dx, dy);
+                if (back) {
+                    dx = -dx;
+                    dy = -dy;
+                }
                 nxs[o] = cx + dx;
                 nys[o] = cy + dy;
                 want[o] = g.col_key((uint64_t)nxs[o], (uint64_t)nys[o]);
+                if (kSample && !((kSampleCols >> (o0 + o)) & 1u)) nxs[o] = -1;  // off the grid
             }
             find_columns<kNG>(g, ci, nxs, nys, has, fc);
             // round 3: first cells of each column
@@ -1755,13 +1811,17 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
                     const bool loaded = has[o] && (int64_t)fc[o] + j < M;
                     const bool inc = loaded && (kk[o][j] >> g.bz) == want[o];
                     const int64_t dz = (int64_t)(kk[o][j] & g.zmask) - cz;
-                    if (inc && dz >= -1 && dz <= 1) cm |= 1u << (o * kNearK + j);
+                    bool c = inc && dz >= -1 && dz <= 1;
+                    if (back) c = c && is_giant(gbits, fc[o] + (uint32_t)j);
+                    if (c) cm |= 1u << (o * kNearK + j);
                     if (j == kNearK - 1 && inc && dz < 1) ovf |= 1u << o;
                 }
             }
             // column 0 is (0, +1): its first cell, when it is the next cell,
-            // was decided by the runs pass
+            // was decided by the runs pass; backwards, column (0, -1)'s cell
+            // A - 1 likewise (its last cell, or its first when it has one)
             if (o0 == 0 && fc[0] == (uint32_t)A + 1) cm &= ~1u;
+            if (back && fc[0] + (uint32_t)(kNearK - 1) == (uint32_t)A - 1) cm &= ~(1u << (kNearK - 1));
             // round 4: parents and point ranges of the candidates
             int32_t rb[kCand];
             uint32_t sb[kCand], eb[kCand];
@@ -1786,6 +1846,8 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
                 need |= (uint32_t)nd << i;
                 if (nd) quick |= (uint32_t)joined(pa.x, pa.y, pa.z, spts[sb[i]], d2) << i;
             }
+            // the sampling links: joined first points only
+            if (kSample) need &= quick;
 #pragma unroll
             for (int i = 0; i < kCand; ++i) {
                 if (!((need >> i) & 1u)) continue;
@@ -1800,6 +1862,7 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
                     ra = uf_link_roots(cpar, uf_find(cpar, ra), r);
                 }
             }
+            if (kSample) continue;
             FEC_COUNT(P, 4, __popc(ovf));
             // columns with cells in reach beyond the loaded ones: at most
             // three more (z within cz +- 1, distinct), from the first one
@@ -1824,6 +1887,7 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
                         const int64_t dz = (int64_t)(kx[j] & g.zmask) - cz;
                         if (dz > 1) break;
                         if (dz < -1) continue;
+                        if (back && (B == (uint32_t)A - 1 || !is_giant(gbits, B))) continue;
                         const int32_t r = uf_find(cpar, (int32_t)B);
                         if (r == ra) continue;
                         const uint32_t sB = cell_start[B];
@@ -1835,8 +1899,9 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
             }
         }
     }
-    defer_flush<BLK>(dq, &P->ndefer[0], defer, defer_cap, spts, cell_start, cpar, frames,
-                     cell_frame, batched, d2_one);
+    if (!kSample)
+        defer_flush<BLK>(dq, &P->ndefer[0], defer, defer_cap, spts, cell_start, cpar, frames,
+                         cell_frame, batched, d2_one);
 }
 
 // The pairs a hooking kernel queued (the first min(count, capacity) entries
@@ -1863,9 +1928,13 @@ __global__ __launch_bounds__(kBlock) void k_deferred(const float4 *__restrict__ 
 // Every cell points at its root afterwards.  Runs after all joins (data is
 // coherent at the kernel boundary); each slot is written once, with the
 // root, so concurrent finds only ever see ancestors.
-__global__ __launch_bounds__(kBlock) void k_compress(int32_t *cpar, const Params *__restrict__ P) {
+// `min_cells`: cell tables shorter than this skip it (the sampling round's
+// compression, for large tables only).
+__global__ __launch_bounds__(kBlock) void k_compress(int32_t *cpar, const Params *__restrict__ P,
+                                                     int64_t min_cells) {
     if (P->status != kStatusOk) return;
     const int64_t M = P->M;
+    if (M < min_cells) return;
     for (int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x; x < M;
          x += (int64_t)gridDim.x * kBlock) {
         cpar[x] = uf_find(cpar, (int32_t)x);
@@ -1879,8 +1948,8 @@ constexpr int kGiantSlots = 8192;
 
 __global__ __launch_bounds__(1024) void k_giant(const int32_t *__restrict__ cpar,
                                                 Frame *__restrict__ frames,
-                                                Params *__restrict__ P) {
-    if (P->status != kStatusOk) return;
+                                                Params *__restrict__ P, int64_t min_cells) {
+    if (P->status != kStatusOk || P->M < min_cells) return;
     __shared__ int32_t t_key[kGiantSlots];
     __shared__ uint32_t t_cnt[kGiantSlots];
     __shared__ uint64_t s_best[1024 / 64];
@@ -1945,21 +2014,25 @@ __global__ __launch_bounds__(1024) void k_giant(const int32_t *__restrict__ cpar
     }
 }
 
-// Bitmap of the cells in the giant component (after the near shell) and
-// the list of the others (the far-shell work list).  Each block takes one
-// contiguous chunk of cells: it counts its list entries, reserves them with
-// one atomic, then writes them (a counter bumped per 256 cells would be a
-// hot spot).
+// Bitmap of the cells in the giant component and the list of the others:
+// after the sampling links (`which` 0: the near-shell work list, large cell
+// tables only, count in P->nwork0) and after the near shell (`which` 1: the
+// far-shell work list, count in P->nwork).  Each block takes one contiguous
+// chunk of cells: it counts its list entries, reserves them with one
+// atomic, then writes them (a counter bumped per 256 cells would be a hot
+// spot).
 __global__ __launch_bounds__(kBlock) void k_nongiant(const int32_t *__restrict__ cpar,
                                                      uint64_t *__restrict__ gbits,
                                                      uint32_t *__restrict__ work,
                                                      const Frame *__restrict__ frames,
                                                      const uint32_t *__restrict__ cell_frame,
-                                                     Params *__restrict__ P) {
+                                                     Params *__restrict__ P, int which) {
     if (P->status != kStatusOk) return;
     __shared__ uint32_t s_wcnt[kBlock / 64];
     __shared__ uint32_t s_base;
     const int64_t M = P->M;
+    if (which == 0 && M < kNearSplitBelow) return;
+    uint32_t *nwork = which == 0 ? &P->nwork0 : &P->nwork;
     const bool batched = P->nframes > 1;
     const int32_t giant_one = P->giant;
     // in the giant component of its frame
@@ -1989,7 +2062,7 @@ __global__ __launch_bounds__(kBlock) void k_nongiant(const int32_t *__restrict__
     if (threadIdx.x == 0) {
         uint32_t tot = 0;
         for (int i = 0; i < kBlock / 64; ++i) tot += s_wcnt[i];
-        s_base = tot ? atomicAdd(&P->nwork, tot) : 0u;
+        s_base = tot ? atomicAdd(nwork, tot) : 0u;
     }
     __syncthreads();
     uint32_t base = s_base;
@@ -2018,9 +2091,6 @@ __global__ __launch_bounds__(kBlock) void k_nongiant(const int32_t *__restrict__
 // and dy > 0, or dx == dy == 0 and dz > 0) or the second cell is inside it.
 // So every far pair with at least one cell outside the giant component is
 // handled; pairs with both cells inside are already joined.
-__device__ __forceinline__ bool is_giant(const uint64_t *__restrict__ gbits, uint32_t B) {
-    return (gbits[B >> 6] >> (B & 63)) & 1ull;
-}
 
 // Work lists shorter than this are cut into one task per column group
 // (a small cloud leaves most of the chip idle, and each lane's chain of
@@ -2438,13 +2508,15 @@ std::atomic<int32_t> g_cell_blocks{kDefaultCellBlocks};
 std::atomic<int32_t> g_stream_blocks{kDefaultStreamBlocks};
 std::atomic<int32_t> g_radix_bits{kDefaultRadixBits};
 std::atomic<int32_t> g_hook_block{kDefaultHookBlock};
+std::atomic<int32_t> g_near_sampling{0};
 }  // namespace
 
 Tuning tuning() {
     return Tuning{g_cell_blocks.load(std::memory_order_relaxed),
                   g_stream_blocks.load(std::memory_order_relaxed),
                   g_radix_bits.load(std::memory_order_relaxed),
-                  g_hook_block.load(std::memory_order_relaxed)};
+                  g_hook_block.load(std::memory_order_relaxed),
+                  g_near_sampling.load(std::memory_order_relaxed)};
 }
 
 void set_tuning(Tuning t) {
@@ -2452,12 +2524,14 @@ void set_tuning(Tuning t) {
     g_stream_blocks.store(t.stream_blocks, std::memory_order_relaxed);
     g_radix_bits.store(t.radix_bits, std::memory_order_relaxed);
     g_hook_block.store(t.hook_block, std::memory_order_relaxed);
+    g_near_sampling.store(t.near_sampling, std::memory_order_relaxed);
 }
 
 const char *stage_name(int s) {
     static const char *names[kNumStages] = {
         "bbox",       "plan",      "keys",       "sort_hist",   "sort_scan",    "sort_scatter",
-        "gather",     "tile_scan", "cells",      "colgrid",     "runs",         "hook_near",
+        "gather",     "tile_scan", "cells",      "colgrid",     "runs",         "sample",
+        "giant_0",    "hook_near",
         "deferred",   "compress_1", "giant",     "work_list",  "hook_far",    "compress_2",
         "final_cells", "final_labels", "finish"};
     return (s >= 0 && s < kNumStages) ? names[s] : "";
@@ -2593,35 +2667,50 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     FEC_LAUNCH(kStRuns, k_runs1<<<(unsigned)ntiles, kBlock, 0, st>>>(
                             spts, cell_start, cell_key, heads, blkhead, frames, cell_frame, P));
     FEC_LAUNCH(kStRuns, k_runs2<<<(unsigned)ntiles, kBlock, 0, st>>>(heads, blkhead, cpar, P));
-    // Each shell has a large-table and a small-table form; which one a call
+    // Each shell has large-table and small-table forms; which one a call
     // needs is known on the device only, so both are launched and the other
     // returns at once.  Cells and work cells never outnumber points, so below
     // the thresholds in points the large forms cannot be meant and are not
-    // launched (two launches fewer on small clouds).
-#define FEC_HOOK_NEAR(SPLIT, BLK)                                                          \
-    FEC_LAUNCH(kStHookNear, k_hook_near<SPLIT, BLK><<<nb_cells, BLK, 0, st>>>(               \
-                                spts, cell_start, cell_key, col_key, col_cell, colgrid,      \
-                                colbits, frames, cell_frame, cpar, P, defer, L.defer_cap))
+    // launched (two launches fewer on small clouds).  Whether the near shell
+    // takes the sampling links is decided here, by the number of points.
+#define FEC_HOOK_NEAR(MODE, BLK, GRID)                                                     \
+    FEC_LAUNCH(MODE == kNearSample ? kStSample : kStHookNear,                               \
+               k_hook_near<MODE, BLK><<<GRID, BLK, 0, st>>>(                                \
+                   spts, cell_start, cell_key, col_key, col_cell, colgrid, colbits, gbits,  \
+                   work, frames, cell_frame, cpar, P, defer, L.defer_cap))
+#define FEC_HOOK_NEAR_ALL(MODE, GRID)                                                      \
+    do {                                                                                   \
+        if (hook_block == 64) FEC_HOOK_NEAR(MODE, 64, GRID);                               \
+        else if (hook_block == 128) FEC_HOOK_NEAR(MODE, 128, GRID);                        \
+        else FEC_HOOK_NEAR(MODE, 256, GRID);                                               \
+    } while (0)
 #define FEC_HOOK_FAR(SPLIT, BLK)                                                           \
     FEC_LAUNCH(kStHookFar, k_hook_far<SPLIT, BLK><<<nb_cells, BLK, 0, st>>>(                 \
                                spts, cell_start, cell_key, col_key, col_cell, colgrid,       \
                                colbits, gbits, work, frames, cell_frame, cpar, P, defer,     \
                                L.defer_cap))
-    if (n >= kNearSplitBelow) {
-        if (hook_block == 64) FEC_HOOK_NEAR(false, 64);
-        else if (hook_block == 128) FEC_HOOK_NEAR(false, 128);
-        else FEC_HOOK_NEAR(false, 256);
+    const bool sampled = n >= kNearSplitBelow &&
+                         (tn.near_sampling == 1 || (tn.near_sampling == 0 && n >= kSampleMinPoints));
+    if (n >= kNearSplitBelow && !sampled) FEC_HOOK_NEAR_ALL(kNearAll, nb_cells);
+    if (sampled) {
+        // sampling links, their giant component and work list, then the near
+        // shell on that list
+        FEC_HOOK_NEAR_ALL(kNearSample, nb_cells);
+        FEC_LAUNCH(kStGiant0, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P, kNearSplitBelow));
+        FEC_LAUNCH(kStGiant0, k_giant<<<(unsigned)nframes, 1024, 0, st>>>(cpar, frames, P,
+                                                                          kNearSplitBelow));
+        FEC_LAUNCH(kStGiant0, k_nongiant<<<nb_cells, kBlock, 0, st>>>(cpar, gbits, work, frames,
+                                                                       cell_frame, P, 0));
+        FEC_HOOK_NEAR_ALL(kNearWork, nb_cells);
     }
-    if (hook_block == 64) FEC_HOOK_NEAR(true, 64);
-    else if (hook_block == 128) FEC_HOOK_NEAR(true, 128);
-    else FEC_HOOK_NEAR(true, 256);
+    FEC_HOOK_NEAR_ALL(kNearSplit, nb_cells);
     FEC_LAUNCH(kStDeferred, k_deferred<<<nb_cells, kBlock, 0, st>>>(
                                 spts, cell_start, frames, cell_frame, cpar, P, defer,
                                 L.defer_cap, 0));
-    FEC_LAUNCH(kStCompress1, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P));
-    FEC_LAUNCH(kStGiant, k_giant<<<(unsigned)nframes, 1024, 0, st>>>(cpar, frames, P));
+    FEC_LAUNCH(kStCompress1, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P, 0));
+    FEC_LAUNCH(kStGiant, k_giant<<<(unsigned)nframes, 1024, 0, st>>>(cpar, frames, P, 0));
     FEC_LAUNCH(kStWorkList, k_nongiant<<<nb_cells, kBlock, 0, st>>>(cpar, gbits, work, frames,
-                                                                     cell_frame, P));
+                                                                     cell_frame, P, 1));
     if (n >= (int64_t)kFarSplitBelow) {
         if (hook_block == 64) FEC_HOOK_FAR(false, 64);
         else if (hook_block == 128) FEC_HOOK_FAR(false, 128);
@@ -2631,11 +2720,12 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     else if (hook_block == 128) FEC_HOOK_FAR(true, 128);
     else FEC_HOOK_FAR(true, 256);
 #undef FEC_HOOK_NEAR
+#undef FEC_HOOK_NEAR_ALL
 #undef FEC_HOOK_FAR
     FEC_LAUNCH(kStDeferred, k_deferred<<<nb_cells, kBlock, 0, st>>>(
                                 spts, cell_start, frames, cell_frame, cpar, P, defer,
                                 L.defer_cap, 1));
-    FEC_LAUNCH(kStCompress2, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P));
+    FEC_LAUNCH(kStCompress2, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P, 0));
     FEC_LAUNCH(kStFinalCells, k_final_cells<<<nb_cells, kBlock, 0, st>>>(
                                   cpar, cell_start, sorig, csize, ccanon, P));
     FEC_LAUNCH(kStFinalLabels, k_labels_clear<<<nb_stream, kBlock, 0, st>>>(labels_out, n, P));

@@ -83,9 +83,9 @@ struct Params {
     int64_t M;            // occupied cells
     int64_t Mcol;         // occupied columns (cells sharing cx, cy)
     int32_t dense_cols;   // 1: column lookups through the dense (cx, cy) index
-    int32_t giant;        // root of the largest component after sampling (-1: none)
-    uint32_t nwork;       // cells outside that component (full-stencil work list)
-    uint32_t pad1;
+    int32_t giant;        // root of the largest component (-1: none)
+    uint32_t nwork;       // cells outside it after the near shell (far-shell work list)
+    uint32_t nwork0;      // cells outside it after the sampling links (near-shell work list)
     // Cell pairs whose first points are not joined, queued by the near and
     // the far shell for a full test once the shell's other joins are in.
     uint32_t ndefer[2];
@@ -193,6 +193,8 @@ enum Stage : int {
     kStCells,
     kStColGrid,
     kStRuns,
+    kStSample,
+    kStGiant0,
     kStHookNear,
     kStDeferred,
     kStCompress1,
@@ -243,6 +245,7 @@ struct Tuning {
     int32_t stream_blocks;
     int32_t radix_bits;  // bits per radix-sort pass (8 .. 11)
     int32_t hook_block;  // threads per block of the hooking kernels (64, 128, 256)
+    int32_t near_sampling;  // sampling links before the near shell: 0 by size, 1 on, 2 off
 };
 constexpr int32_t kDefaultCellBlocks = kCellBlocks;
 constexpr int32_t kDefaultStreamBlocks = 4096;

@@ -1,6 +1,6 @@
 """Autotuner for the launch configuration of the clustering kernels.
 
-Four knobs change how the work is laid out on the chip, never the result:
+Five knobs change how the work is laid out on the chip, never the result:
 
 * ``cell_blocks``   -- blocks of the per-cell grid-stride kernels (near and
   far shells, compression, finalize);
@@ -8,12 +8,15 @@ Four knobs change how the work is laid out on the chip, never the result:
 * ``radix_bits``    -- bits per radix-sort pass (8 to 11: fewer passes over
   larger per-tile tables);
 * ``hook_block``    -- threads per block of the hooking kernels (64, 128,
-  256).
+  256);
+* ``near_sampling`` -- sampled links before the near shell, which then runs
+  only outside the giant component they form: 0 by cloud size (2^23 points
+  or more), 1 on, 2 off.
 
 ``autotune`` times candidate configurations on a representative cloud, checks
 that all give the same labels, and keeps the fastest: by default a coordinate
 search (each knob over its values with the others at the best so far, in the
-order radix_bits, hook_block, cell_blocks, stream_blocks), or every
+order near_sampling, radix_bits, hook_block, cell_blocks, stream_blocks), or every
 configuration of an explicit candidate list.  The choice is cached in a JSON
 file keyed by GPU architecture and size bucket (log2 of the point count), and
 ``apply`` sets the cached configuration for a coming call.
@@ -34,15 +37,16 @@ import time
 
 from . import cluster_async, get_tuning, new_workspace, set_tuning
 
-KNOBS = ("cell_blocks", "stream_blocks", "radix_bits", "hook_block")
+KNOBS = ("cell_blocks", "stream_blocks", "radix_bits", "hook_block", "near_sampling")
 VALUES = {
     "cell_blocks": (1024, 2048, 4096, 8192, 16384),
     "stream_blocks": (2048, 4096, 8192),
     "radix_bits": (8, 9, 10, 11),
     "hook_block": (64, 128, 256),
+    "near_sampling": (1, 2),
 }
-SEARCH_ORDER = ("radix_bits", "hook_block", "cell_blocks", "stream_blocks")
-DEFAULT = (4096, 4096, 9, 256)
+SEARCH_ORDER = ("near_sampling", "radix_bits", "hook_block", "cell_blocks", "stream_blocks")
+DEFAULT = (4096, 4096, 9, 256, 0)
 
 
 def cache_path() -> str:
@@ -76,7 +80,7 @@ def _key(arch: str, n: int) -> str:
 
 
 def _full(cfg) -> tuple:
-    """A configuration as all four knobs (missing trailing knobs: defaults)."""
+    """A configuration as all five knobs (missing trailing knobs: defaults)."""
     cfg = tuple(int(v) for v in cfg)
     return cfg + DEFAULT[len(cfg):]
 
@@ -96,7 +100,7 @@ def record(arch: str, n: int, cfg, ms: float, path: str | None = None) -> None:
 
 
 def lookup(arch: str, n: int, path: str | None = None):
-    """The cached configuration (four knobs) for (arch, size bucket of n), or None."""
+    """The cached configuration (five knobs) for (arch, size bucket of n), or None."""
     e = _load_cache(path or cache_path()).get(_key(arch, n))
     if e is None:
         return None
@@ -106,7 +110,7 @@ def lookup(arch: str, n: int, path: str | None = None):
 def apply(n: int, device="cuda:0", path: str | None = None) -> tuple:
     """Sets the cached configuration for n points (the defaults when none is cached)."""
     cfg = lookup(_arch(device), n, path)
-    set_tuning(*(cfg or (0, 0, 0, 0)))
+    set_tuning(*(cfg or (0, 0, 0, 0, 0)))
     return get_tuning()
 
 
@@ -120,9 +124,9 @@ def autotune(xyz, d: float, min_size: int = 1, max_size: int = 2**31 - 1,
     tensor), checks that all give the same labels, caches and applies the
     fastest.
 
-    ``candidates``: explicit configurations (tuples of up to four knobs,
+    ``candidates``: explicit configurations (tuples of up to five knobs,
     missing ones at their defaults), all timed; None: the coordinate search.
-    Returns {"best": four knobs, "ms": {"c/s/r/h": ms}}.  ``timer(fn, steps)``
+    Returns {"best": five knobs, "ms": {"c/s/r/h/s": ms}}.  ``timer(fn, steps)``
     may replace the wall-clock timing (for tests).
     """
     import torch
@@ -177,7 +181,8 @@ def autotune(xyz, d: float, min_size: int = 1, max_size: int = 2**31 - 1,
                 for v in VALUES[knob]:
                     cfg = best[:i] + (v,) + best[i + 1:]
                     measure(cfg)
-                best = min((c for c in times if all(c[j] == best[j] for j in range(4) if j != i)),
+                best = min((c for c in times
+                            if all(c[j] == best[j] for j in range(len(KNOBS)) if j != i)),
                            key=times.get)
     finally:
         set_tuning(*saved)

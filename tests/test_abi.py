@@ -166,23 +166,24 @@ def test_server_host_side_checks(fec):
 
 def test_tuning_knobs_and_cache(fec, tmp_path):
     from paper_2208_07678_amd import tune
-    assert fec.get_tuning() == tune.DEFAULT == (4096, 4096, 9, 256)
-    fec.set_tuning(1024, 8192, 9, 128)
-    assert fec.get_tuning() == (1024, 8192, 9, 128)
-    fec.set_tuning(1024, 8192)          # radix and block back to their defaults
-    assert fec.get_tuning() == (1024, 8192, 9, 256)
-    for bad in [(-1, 0), (0, 1 << 21), (0, 0, 7), (0, 0, 12), (0, 0, 0, 96), (0, 0, 0, 512)]:
+    assert fec.get_tuning() == tune.DEFAULT == (4096, 4096, 9, 256, 0)
+    fec.set_tuning(1024, 8192, 9, 128, 2)
+    assert fec.get_tuning() == (1024, 8192, 9, 128, 2)
+    fec.set_tuning(1024, 8192)          # the other knobs back to their defaults
+    assert fec.get_tuning() == (1024, 8192, 9, 256, 0)
+    for bad in [(-1, 0), (0, 1 << 21), (0, 0, 7), (0, 0, 12), (0, 0, 0, 96), (0, 0, 0, 512),
+                (0, 0, 0, 0, -1), (0, 0, 0, 0, 3)]:
         with pytest.raises(fec.FecError):
             fec.set_tuning(*bad)
-    fec.set_tuning(0, 0, 0, 0)
-    assert fec.get_tuning() == (4096, 4096, 9, 256)
+    fec.set_tuning(0, 0, 0, 0, 0)
+    assert fec.get_tuning() == (4096, 4096, 9, 256, 0)
     # cache round trip, keyed by arch and size bucket
     p = str(tmp_path / "tune.json")
     assert tune.lookup("gfx950", 27_000_000, p) is None
-    tune.record("gfx950", 27_000_000, (2048, 8192, 9, 128), 6.1, p)
-    assert tune.lookup("gfx950", 20_000_000, p) == (2048, 8192, 9, 128)  # same bucket (2^24)
+    tune.record("gfx950", 27_000_000, (2048, 8192, 9, 128, 1), 6.1, p)
+    assert tune.lookup("gfx950", 20_000_000, p) == (2048, 8192, 9, 128, 1)  # same bucket (2^24)
     tune.record("gfx950", 1000, (2048, 8192), 0.2, p)   # knobs not given: defaults
-    assert tune.lookup("gfx950", 1000, p) == (2048, 8192, 9, 256)
+    assert tune.lookup("gfx950", 1000, p) == (2048, 8192, 9, 256, 0)
     assert tune.lookup("gfx950", 40_000_000, p) is None            # next bucket
     assert tune.lookup("gfx942", 27_000_000, p) is None
     assert tune.bucket(1) == 0 and tune.bucket(4096) == 12

@@ -4,6 +4,8 @@ oracle's element by element, filtered (sizes 100..5,000,000) and
 unfiltered, and the kept and total cluster counts agree.  The oracle clusters
 the whole map once (single-threaded, about a minute) and gives both
 labellings from that one run.  The same call repeated is bitwise identical.
+At this size the near shell takes the sampling links by default; the call
+with them switched off must give the same labels.
 """
 
 import time
@@ -32,10 +34,23 @@ def test_map27m_full_size_equals_oracle():
     filt_t, kf = fec.cluster(t, d, mn, mx, workspace=ws)
     again_t, kf2 = fec.cluster(t, d, mn, mx, workspace=ws)
     torch.cuda.synchronize()
+    st = fec.workspace_stats(ws)
+    say("stats", st)
+    # the sampled form ran: its work list is part of the cells
+    assert 0 < st["near_work_cells"] < st["cells"]
+    try:
+        fec.set_tuning(near_sampling=2)
+        plain_t, kp = fec.cluster(t, d, mn, mx, workspace=ws)
+        torch.cuda.synchronize()
+        assert fec.workspace_stats(ws)["near_work_cells"] == 0
+    finally:
+        fec.set_tuning()
     unf, filt, again = unf_t.cpu().numpy(), filt_t.cpu().numpy(), again_t.cpu().numpy()
-    del t, ws, unf_t, filt_t, again_t
+    plain = plain_t.cpu().numpy()
+    del t, ws, unf_t, filt_t, again_t, plain_t
     say("gpu done: components", ku, "kept", kf)
     assert np.array_equal(filt, again) and kf == kf2
+    assert np.array_equal(filt, plain) and kf == kp
     say("oracle on the whole map")
     t0 = time.perf_counter()
     want, wk, want_unf, wcomp = oracle.fec_both(xyz, d, mn, mx)

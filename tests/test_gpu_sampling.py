@@ -1,0 +1,100 @@
+"""GPU parity of the near shell's forms on large cell tables.
+
+Clouds of 131,072 cells or more either run the near shell on every cell, or
+first link each cell to the first cells of its dx = +1 neighbour columns
+(when their first points are joined), find the largest component those links
+form, and run the near shell only on the cells outside it (forward pairs,
+and backward pairs towards that component).  The launch configuration picks
+the form (``near_sampling``: 0 by cloud size, 1 on, 2 off); both must give
+the oracle's labels exactly, on single clouds and on batches, where every
+frame has its own largest component.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import describe_mismatch, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _cluster(xyz, d, mn, mx, sampling):
+    import torch
+
+    import paper_2208_07678_amd as fec
+    t = torch.from_numpy(np.ascontiguousarray(xyz, dtype=np.float32)).to("cuda:0")
+    ws = fec.new_workspace(t.shape[0], t.device)
+    fec.set_tuning(near_sampling=sampling)
+    try:
+        labels, k = fec.cluster(t, d, mn, mx, workspace=ws)
+        torch.cuda.synchronize()
+        st = fec.workspace_stats(ws)
+    finally:
+        fec.set_tuning()
+    return labels.cpu().numpy(), k, st
+
+
+CASES = [
+    ("map 6 frames", lambda: synth.lidar_map(frames=list(range(6))), 0.2, 100, 5000000),
+    ("map 6 frames shuffled", lambda: synth.lidar_map(frames=list(range(6)))[
+        np.random.default_rng(3).permutation(6 * 135000)], 0.2, 100, 5000000),
+    ("map frames 40..45, unfiltered", lambda: synth.lidar_map(frames=list(range(40, 46))),
+     0.2, 1, 10000000),
+    ("dense plane", lambda: synth.random_cloud(300000, extent=(50.0, 50.0, 0.05), seed=13),
+     0.15, 1, 300000),
+    ("two dense layers", lambda: np.concatenate([
+        synth.random_cloud(150000, extent=(30.0, 30.0, 0.05), seed=31),
+        synth.random_cloud(150000, extent=(30.0, 30.0, 0.05), seed=32, offset=(0, 0, 0.3))]),
+     0.16, 2, 300000),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_near_shell_forms_match_oracle(case):
+    tag, make, d, mn, mx = case
+    xyz = make()
+    want, wk = oracle.fec(xyz, d, mn, mx)
+    for sampling in (1, 2, 0):
+        say("case", tag, "n=%d" % xyz.shape[0], "near_sampling", sampling)
+        got, k, st = _cluster(xyz, d, mn, mx, sampling)
+        say("stats", {k_: st[k_] for k_ in ("cells", "near_work_cells", "work_cells")})
+        assert st["cells"] >= 131072, "the case must reach the large-table forms"
+        assert np.array_equal(got, want), "%s sampling %d: %s" % (
+            tag, sampling, describe_mismatch(got, want))
+        assert k == wk
+        if sampling == 1:
+            assert 0 < st["near_work_cells"] <= st["cells"]
+        else:   # off, or by size (these clouds are below 2^23 points)
+            assert st["near_work_cells"] == 0
+
+
+def test_batch_with_sampling_matches_oracle():
+    import torch
+
+    import paper_2208_07678_amd as fec
+    frames, ds, mn, mx = synth.make_batch_config("batch64")
+    frames, ds = frames[:24], ds[:24]
+    want = [oracle.fec(f, d, mn, mx) for f, d in zip(frames, ds)]
+    xyz, offs = fec.pack_frames([torch.from_numpy(f).to("cuda:0") for f in frames])
+    for sampling in (1, 2):
+        say("batch of", len(frames), "frames, n=%d" % xyz.shape[0], "near_sampling", sampling)
+        ws = fec.new_batch_workspace(xyz.shape[0], len(frames), xyz.device)
+        fec.set_tuning(near_sampling=sampling)
+        try:
+            labels, ks = fec.cluster_batch(xyz, offs, list(ds), mn, mx, workspace=ws)
+            torch.cuda.synchronize()
+            st = fec.workspace_stats(ws)
+        finally:
+            fec.set_tuning()
+        say("stats", {k_: st[k_] for k_ in ("cells", "near_work_cells", "work_cells")})
+        assert st["cells"] >= 131072
+        assert (st["near_work_cells"] > 0) == (sampling == 1)
+        got = labels.cpu().numpy()
+        o = offs.cpu().numpy()
+        for b, (wl, wk) in enumerate(want):
+            gl = got[o[b]:o[b + 1]]
+            assert np.array_equal(gl, wl), "frame %d sampling %d: %s" % (
+                b, sampling, describe_mismatch(gl, wl))
+            assert ks[b] == wk
