@@ -42,11 +42,32 @@ ALG_BYTES_PER_POINT = {
     "cells": 8.0,        # the cell table: sorted keys read once, cell starts and keys written
     # hooking: every point read once (16) plus parent initialisation and
     # unions (12); the far shell visits only the cells outside the giant
-    # component, so its share is scaled by work cells / cells
+    # component, so its share is scaled by work cells / cells, and so is the
+    # near shell's when it runs on the sampled links' work list
     "hook_near": 28.0,
     "hook_far": 28.0,
     "final_labels": 4.0,  # write every label once (-1 pass); kept clusters' labels again
 }
+# Stages whose work is per cell, not per point: bytes per cell.
+ALG_BYTES_PER_CELL = {
+    # the sampling links: each cell's key, point range, parent and first
+    # point read once (8 + 4 + 4 + 16)
+    "sample": 32.0,
+}
+
+
+def alg_bytes_per_point(stage: str, stats: dict, n: int) -> float:
+    """The byte model of `stage` per point of the cloud, for the call whose
+    workspace statistics are `stats` (the work lists scale the shells)."""
+    cells = max(stats.get("cells") or 1, 1)
+    if stage in ALG_BYTES_PER_CELL:
+        return ALG_BYTES_PER_CELL[stage] * cells / max(n, 1)
+    bpp = ALG_BYTES_PER_POINT.get(stage, 16.0)
+    if stage == "hook_far":
+        bpp *= (stats.get("work_cells") or 0) / cells
+    elif stage == "hook_near" and (stats.get("near_work_cells") or 0) > 0:
+        bpp *= stats["near_work_cells"] / cells
+    return bpp
 # The whole path per point (survey byte model of the specified pipeline with
 # 64-bit keys): the figure the path's algorithmic HBM fraction is taken on.
 PATH_ALG_BYTES_PER_POINT = 260.0
@@ -54,6 +75,7 @@ PATH_ALG_BYTES_PER_POINT = 260.0
 LIMITER = {
     "hook_near": "latency: chains of dependent loads and device-scope compare-and-swap",
     "hook_far": "latency: chains of dependent loads and device-scope compare-and-swap",
+    "sample": "latency: dependent loads and device-scope compare-and-swap",
     "runs": "latency: dependent loads",
 }
 
@@ -164,7 +186,9 @@ def path_traffic(workload: str, passes: int):
         return None
     tot = 0
     for st, k in rec.get("kernels", {}).items():
-        mult = passes if st.startswith("sort") else (2 if st == "compress" else 1)
+        # sort stages: per working pass; the others per launch, or per call
+        # where a call launches them more than once
+        mult = passes if st.startswith("sort") else 1
         tot += k["hbm_bytes_per_launch"] * mult
     return tot
 
@@ -271,7 +295,7 @@ def batch_result(args) -> dict:
     dst = fec.workspace_stats(ws)
     work_launches = (dst.get("radix_passes") or 1) if dominant.startswith("sort") else 1
     avg_launch_ms = dom_ms / args.steps / work_launches
-    bytes_per_launch = ALG_BYTES_PER_POINT.get(dominant, 16.0) * n
+    bytes_per_launch = alg_bytes_per_point(dominant, dst, n) * n
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
     out = {
         "metric": "frames/s clustered (64-frame batch)",
@@ -715,9 +739,7 @@ def main():
     avg_launch_ms = dom_ms / args.steps / max(work_launches, 1)
     # stages without a per-point byte model are reported against HBM with the
     # bytes of their cells' points read once (a lower bound)
-    bpp = ALG_BYTES_PER_POINT.get(dominant, 16.0)
-    if dominant == "hook_far":
-        bpp *= (stats.get("work_cells") or 0) / max(stats.get("cells") or 1, 1)
+    bpp = alg_bytes_per_point(dominant, stats, n)
     bytes_per_launch = bpp * n
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -765,6 +787,7 @@ def main():
                    "mean_points_per_cell": n / max(stats.get("cells") or 1, 1),
                    "radix_passes": stats.get("radix_passes"),
                    "work_cells": stats.get("work_cells"),
+                   "near_work_cells": stats.get("near_work_cells"),
                    "launch_config": dict(zip(("cell_blocks", "stream_blocks", "radix_bits", "hook_block", "near_sampling"), fec.get_tuning())),
                    "autotuned": tuned is not None},
         "roofline": roofline,

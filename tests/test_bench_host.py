@@ -46,8 +46,9 @@ def test_traffic_only_for_its_workload_and_sources(tmp_path, monkeypatch):
     # another workload has no counters of its own
     assert bench.measured_traffic("lidar120k", "hook_near") is None
     assert bench.path_traffic("lidar120k", 5) is None
-    # sort kernels once per pass, compress twice, the rest once
-    assert bench.path_traffic("map27m", 5) == 100 + 5 * (10 + 20) + 2 * 3 + 7
+    # sort kernels once per pass, the rest once (kernels launched several
+    # times per call are recorded per call)
+    assert bench.path_traffic("map27m", 5) == 100 + 5 * (10 + 20) + 3 + 7
     # a record filed under one name but taken on another workload
     with open(tmp_path / "profiles" / "traffic_batch64.json", "w") as f:
         json.dump(_record("map27m", digest), f)
@@ -75,3 +76,17 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120, cwd=ROOT)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_byte_models_follow_the_work_lists():
+    n = 1000
+    st = {"cells": 400, "work_cells": 100, "near_work_cells": 0}
+    assert bench.alg_bytes_per_point("gather", st, n) == 40.0
+    assert bench.alg_bytes_per_point("hook_near", st, n) == 28.0
+    assert bench.alg_bytes_per_point("hook_far", st, n) == 28.0 * 100 / 400
+    # the near shell on the sampled links' work list
+    st["near_work_cells"] = 200
+    assert bench.alg_bytes_per_point("hook_near", st, n) == 28.0 * 200 / 400
+    # the sampling links: per cell
+    assert bench.alg_bytes_per_point("sample", st, n) == 32.0 * 400 / 1000
+    assert bench.alg_bytes_per_point("no_model", st, n) == 16.0
