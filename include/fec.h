@@ -298,8 +298,9 @@ int32_t fec_stage_count(void);
  *   near_sampling  whether clouds of at least 131,072 cells first link each
  *                  cell to the first cells of its dx = +1 neighbour columns
  *                  and run the near shell only outside the largest component
- *                  so formed: 0 when the cloud has at least 2^23 points
- *                  (default), 1 always, 2 never.
+ *                  so formed: 0 when the cloud (in a batch, the average
+ *                  frame) has at least 2^23 points (default), 1 always,
+ *                  2 never.
  * 0 restores a knob's default.  Labels and counts do not depend on any of
  * them.  Returns FEC_OK, or FEC_EINVAL for a value outside its set.
  */

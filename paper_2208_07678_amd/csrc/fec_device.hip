@@ -1696,7 +1696,10 @@ constexpr int kNearSplit = 0, kNearAll = 1, kNearSample = 2, kNearWork = 3;
 // (with no retry a root takes at most one hook, and the trees stay small).
 constexpr uint32_t kSampleCols = 0xEu;
 // Clouds of at least this many points take the sampling links (unless the
-// launch configuration says otherwise, see fec_tuning_set).  They pay
+// launch configuration says otherwise, see fec_tuning_set); in a batch, the
+// frames' average decides (the ground of each frame is what sampling
+// joins, and a batch of small frames has the small frames' thin ground).
+// They pay
 // where the near shell's cells in the giant component are expensive, on
 // dense accumulated ground (27 M-point map: sampling, near shell, queued
 // pairs and compression 1.53 -> 1.43 ms, call 4.20 -> 4.06 ms); on single
@@ -2689,8 +2692,9 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
                                spts, cell_start, cell_key, col_key, col_cell, colgrid,       \
                                colbits, gbits, work, frames, cell_frame, cpar, P, defer,     \
                                L.defer_cap))
-    const bool sampled = n >= kNearSplitBelow &&
-                         (tn.near_sampling == 1 || (tn.near_sampling == 0 && n >= kSampleMinPoints));
+    const bool sampled =
+        n >= kNearSplitBelow &&
+        (tn.near_sampling == 1 || (tn.near_sampling == 0 && n / nframes >= kSampleMinPoints));
     if (n >= kNearSplitBelow && !sampled) FEC_HOOK_NEAR_ALL(kNearAll, nb_cells);
     if (sampled) {
         // sampling links, their giant component and work list, then the near

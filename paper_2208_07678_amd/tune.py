@@ -11,7 +11,7 @@ Five knobs change how the work is laid out on the chip, never the result:
   256);
 * ``near_sampling`` -- sampled links before the near shell, which then runs
   only outside the giant component they form: 0 by cloud size (2^23 points
-  or more), 1 on, 2 off.
+  or more; in a batch, the average frame's), 1 on, 2 off.
 
 ``autotune`` times candidate configurations on a representative cloud, checks
 that all give the same labels, and keeps the fastest: by default a coordinate
