@@ -1851,11 +1851,23 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
             }
             // the sampling links: joined first points only
             if (kSample) need &= quick;
+            // candidates whose parent (their run's first cell) is that of a
+            // candidate already joined to A's component need no search: a
+            // cached read of the parent just hooked may still show it as a
+            // root, and its hook would only fail
+            uint32_t joinedm = 0;
 #pragma unroll
             for (int i = 0; i < kCand; ++i) {
                 if (!((need >> i) & 1u)) continue;
+                bool dup = false;
+#pragma unroll
+                for (int j = 0; j < i; ++j) dup |= ((joinedm >> j) & 1u) && rb[j] == rb[i];
+                if (dup) continue;
                 const int32_t r = uf_find(cpar, rb[i]);
-                if (r == ra) continue;
+                if (r == ra) {
+                    joinedm |= 1u << i;
+                    continue;
+                }
                 FEC_COUNT(P, 1, 1);
                 FEC_COUNT(P, 3, (eA - sA) * (eb[i] - sb[i]));
                 if (((quick >> i) & 1u) ||
@@ -1863,6 +1875,7 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
                      any_joined(spts, sA, eA, sb[i], eb[i], d2))) {
                     FEC_COUNT(P, 2, 1);
                     ra = uf_link_roots(cpar, uf_find(cpar, ra), r);
+                    joinedm |= 1u << i;
                 }
             }
             if (kSample) continue;
@@ -2095,13 +2108,47 @@ __global__ __launch_bounds__(kBlock) void k_nongiant(const int32_t *__restrict__
 // So every far pair with at least one cell outside the giant component is
 // handled; pairs with both cells inside are already joined.
 
+// Occupied columns of the 5x5 neighbourhood of column (cx, cy), from the
+// dense index's occupancy bits (two words per row at most), as a 24-bit
+// mask in the far shell's column order: bit q for q' = (dx + 2) * 5 +
+// (dy + 2), q = q' below the centre (q' = 12, left out) and q' - 1 above.
+__device__ __forceinline__ uint32_t occupied_5x5(const Grid &g, const uint32_t *__restrict__ colbits,
+                                                 int64_t cx, int64_t cy) {
+    const int64_t y0 = cy - 2 < 0 ? 0 : cy - 2;
+    const int64_t y1 = cy + 2 >= g.NY ? g.NY - 1 : cy + 2;
+    uint32_t w0[5], w1[5];
+    int64_t i0[5];
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+        const int64_t x = cx + r - 2;
+        const bool in = x >= 0 && x < g.NX;
+        i0[r] = in ? x * g.NYp + y0 : 0;
+        const int64_t i1 = in ? x * g.NYp + y1 : 0;
+        w0[r] = in ? colbits[i0[r] >> 5] : 0u;
+        w1[r] = in && (i1 >> 5) != (i0[r] >> 5) ? colbits[i1 >> 5] : 0u;
+    }
+    const uint32_t width = (uint32_t)(y1 - y0 + 1), lo = (uint32_t)(y0 - (cy - 2));
+    uint32_t m = 0;
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+        const uint64_t two = ((uint64_t)w1[r] << 32) | w0[r];
+        const uint32_t row = (uint32_t)(two >> (i0[r] & 31)) & ((1u << width) - 1u);
+        m |= row << (r * 5 + lo);
+    }
+    return (m & 0xFFFu) | ((m >> 1) & ~0xFFFu);
+}
+
 // Work lists shorter than this are cut into one task per column group
 // (a small cloud leaves most of the chip idle, and each lane's chain of
 // dependent loads sets the kernel's time); longer ones keep one task per
 // cell (the chip is full, and the tasks' repeated set-up would cost more).
 constexpr uint32_t kFarSplitBelow = 131072;
 
-template <bool kSplit, int BLK>
+// kOcc: the large form for the dense column index, which visits only the
+// occupied columns (see occupied_5x5); the other large form serves the hash
+// and search indexes.  Separate instances keep each one's registers down
+// (one kernel with both paths made the hash form 8 % slower on batches).
+template <bool kSplit, bool kOcc, int BLK>
 __global__ __launch_bounds__(BLK) void k_hook_far(const float4 *__restrict__ spts,
                                                       const uint32_t *__restrict__ cell_start,
                                                       const uint64_t *__restrict__ cell_key,
@@ -2134,7 +2181,9 @@ __global__ __launch_bounds__(BLK) void k_hook_far(const float4 *__restrict__ spt
     constexpr int kK = 1;
     static_assert(kG * kK <= 32, "candidate masks are 32-bit");
     static_assert(kG <= 32 && 24 % kG == 0, "groups cover the 24 columns");
-    if ((nwork < kFarSplitBelow) != kSplit) return;  // the other instance's case
+    if ((nwork < kFarSplitBelow) != kSplit) return;  // another instance's case
+    static_assert(!(kSplit && kOcc), "the occupancy form is a large form");
+    if (!kSplit && (ci.mode == kColDense) != kOcc) return;
     // pairs whose first points are not joined: queued (see DeferLds)
     __shared__ DeferLds dq;
     if (threadIdx.x == 0) dq.n = 0;
@@ -2185,27 +2234,41 @@ __global__ __launch_bounds__(BLK) void k_hook_far(const float4 *__restrict__ spt
             if ((kb >> g.bz) != ck || dz > 2) break;
             if (dz == 2) pair((uint32_t)B, cpar[B]);
         }
-        // the task's groups of kG of the 24 other columns of the 5x5
-        // neighbourhood
+        // the task's columns of the 24 others of the 5x5 neighbourhood, kG
+        // at a time: with the dense index only the occupied ones (a third
+        // of them around the map's work cells), known from the occupancy
+        // bits of the five rows
+        uint32_t todo = kOcc ? occupied_5x5(g, colbits, cx, cy) : 0u;
 #pragma unroll 1
-        for (int grp = kSplit ? task : 0; grp < (kSplit ? task + 1 : (int)kGroups); ++grp) {
-            const int g0 = grp * kG;
+        for (int grp = kSplit ? task : 0;
+             kOcc ? todo != 0u : grp < (kSplit ? task + 1 : (int)kGroups); ++grp) {
             int dxs[kG], dys[kG];
-            bool has[kG];
+            bool has[kG], use[kG];
             uint32_t fc[kG];
             uint64_t want[kG];
             int64_t nxs[kG], nys[kG];
 #pragma unroll
             for (int o = 0; o < kG; ++o) {
-                int q = g0 + o;
+                use[o] = !kOcc || todo != 0u;
+                int q = kOcc ? (use[o] ? __ffs(todo) - 1 : 0) : grp * kG + o;
+                todo &= todo - 1u;
                 q = q >= 12 ? q + 1 : q;  // skip (0, 0)
                 dxs[o] = q / 5 - 2;
                 dys[o] = q % 5 - 2;
-                nxs[o] = cx + dxs[o];
+                nxs[o] = use[o] ? cx + dxs[o] : -1;  // unused slot: off the grid
                 nys[o] = cy + dys[o];
                 want[o] = g.col_key((uint64_t)nxs[o], (uint64_t)nys[o]);
             }
-            find_columns<kG>(g, ci, nxs, nys, has, fc);
+            if (kOcc) {
+                // occupied by construction: only the first cells to load
+#pragma unroll
+                for (int o = 0; o < kG; ++o) {
+                    has[o] = use[o];
+                    fc[o] = use[o] ? ci.colgrid[(uint64_t)(nxs[o] * g.NYp + nys[o])] : 0u;
+                }
+            } else {
+                find_columns<kG>(g, ci, nxs, nys, has, fc);
+            }
             uint64_t kk[kG][kK];
 #pragma unroll
             for (int o = 0; o < kG; ++o)
@@ -2687,8 +2750,8 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
         else if (hook_block == 128) FEC_HOOK_NEAR(MODE, 128, GRID);                        \
         else FEC_HOOK_NEAR(MODE, 256, GRID);                                               \
     } while (0)
-#define FEC_HOOK_FAR(SPLIT, BLK)                                                           \
-    FEC_LAUNCH(kStHookFar, k_hook_far<SPLIT, BLK><<<nb_cells, BLK, 0, st>>>(                 \
+#define FEC_HOOK_FAR(SPLIT, OCC, BLK)                                                      \
+    FEC_LAUNCH(kStHookFar, k_hook_far<SPLIT, OCC, BLK><<<nb_cells, BLK, 0, st>>>(            \
                                spts, cell_start, cell_key, col_key, col_cell, colgrid,       \
                                colbits, gbits, work, frames, cell_frame, cpar, P, defer,     \
                                L.defer_cap))
@@ -2716,13 +2779,20 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     FEC_LAUNCH(kStWorkList, k_nongiant<<<nb_cells, kBlock, 0, st>>>(cpar, gbits, work, frames,
                                                                      cell_frame, P, 1));
     if (n >= (int64_t)kFarSplitBelow) {
-        if (hook_block == 64) FEC_HOOK_FAR(false, 64);
-        else if (hook_block == 128) FEC_HOOK_FAR(false, 128);
-        else FEC_HOOK_FAR(false, 256);
+        if (hook_block == 64) {
+            FEC_HOOK_FAR(false, true, 64);
+            FEC_HOOK_FAR(false, false, 64);
+        } else if (hook_block == 128) {
+            FEC_HOOK_FAR(false, true, 128);
+            FEC_HOOK_FAR(false, false, 128);
+        } else {
+            FEC_HOOK_FAR(false, true, 256);
+            FEC_HOOK_FAR(false, false, 256);
+        }
     }
-    if (hook_block == 64) FEC_HOOK_FAR(true, 64);
-    else if (hook_block == 128) FEC_HOOK_FAR(true, 128);
-    else FEC_HOOK_FAR(true, 256);
+    if (hook_block == 64) FEC_HOOK_FAR(true, false, 64);
+    else if (hook_block == 128) FEC_HOOK_FAR(true, false, 128);
+    else FEC_HOOK_FAR(true, false, 256);
 #undef FEC_HOOK_NEAR
 #undef FEC_HOOK_NEAR_ALL
 #undef FEC_HOOK_FAR
