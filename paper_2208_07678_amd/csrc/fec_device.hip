@@ -1678,7 +1678,7 @@ __device__ __forceinline__ void defer_flush(DeferLds &q, uint32_t *count,
     }
 }
 
-// Is cell B in the giant component of the last k_nongiant (bitmap)?
+// Is cell B in the giant component of the last k_giant_bits (bitmap)?
 __device__ __forceinline__ bool is_giant(const uint64_t *__restrict__ gbits, uint32_t B) {
     return (gbits[B >> 6] >> (B & 63)) & 1ull;
 }
@@ -2030,74 +2030,122 @@ __global__ __launch_bounds__(1024) void k_giant(const int32_t *__restrict__ cpar
     }
 }
 
-// Bitmap of the cells in the giant component and the list of the others:
-// after the sampling links (`which` 0: the near-shell work list, large cell
-// tables only, count in P->nwork0) and after the near shell (`which` 1: the
-// far-shell work list, count in P->nwork).  Each block takes one contiguous
-// chunk of cells: it counts its list entries, reserves them with one
-// atomic, then writes them (a counter bumped per 256 cells would be a hot
-// spot).
-__global__ __launch_bounds__(kBlock) void k_nongiant(const int32_t *__restrict__ cpar,
-                                                     uint64_t *__restrict__ gbits,
-                                                     uint32_t *__restrict__ work,
-                                                     const Frame *__restrict__ frames,
-                                                     const uint32_t *__restrict__ cell_frame,
-                                                     Params *__restrict__ P, int which) {
-    if (P->status != kStatusOk) return;
-    __shared__ uint32_t s_wcnt[kBlock / 64];
-    __shared__ uint32_t s_base;
-    const int64_t M = P->M;
-    if (which == 0 && M < kNearSplitBelow) return;
-    uint32_t *nwork = which == 0 ? &P->nwork0 : &P->nwork;
-    const bool batched = P->nframes > 1;
-    const int32_t giant_one = P->giant;
-    // in the giant component of its frame
-    auto in_giant = [&](int64_t A) {
-        const int32_t gA = batched ? frames[cell_frame[A]].giant : giant_one;
-        return cpar[A] == gA;
-    };
-    const int lane = __lane_id(), wave = threadIdx.x >> 6;
-    // chunk of whole 256-cell groups (keeps the bitmap words aligned)
+// Bitmap of the cells in the giant component and the list of the others, in
+// cell order: after the sampling links (`which` 0: the near-shell work list,
+// large cell tables only, count in P->nwork0) and after the near shell
+// (`which` 1: the far-shell work list, count in P->nwork).  Two kernels on
+// the same grid of at most kListBlocks blocks, each block on one contiguous
+// chunk of whole 256-cell groups: the first writes the bitmap and the
+// block's count of listed cells, the second adds up the counts of the
+// blocks before it and writes its cells from the bitmap.  No atomics: the
+// list comes out sorted, which keeps a shell's neighbouring tasks close in
+// space (with one slot reservation per block the list was a shuffle of
+// chunks, and the far shell 10 % slower), and all blocks reserving at once
+// on one address had queued.
+__device__ __forceinline__ void list_chunk(int64_t M, int64_t &c0, int64_t &c1) {
     const int64_t groups = (M + kBlock - 1) / kBlock;
     const int64_t per = (groups + gridDim.x - 1) / gridDim.x;
-    const int64_t c0 = (int64_t)blockIdx.x * per * kBlock;
-    const int64_t c1 = c0 + per * kBlock < M ? c0 + per * kBlock : M;
-    if (c0 >= c1) return;
+    c0 = (int64_t)blockIdx.x * per * kBlock;
+    c1 = c0 + per * kBlock < M ? c0 + per * kBlock : M;
+}
+
+__global__ __launch_bounds__(kBlock) void k_giant_bits(const int32_t *__restrict__ cpar,
+                                                       uint64_t *__restrict__ gbits,
+                                                       uint32_t *__restrict__ listcnt,
+                                                       const Frame *__restrict__ frames,
+                                                       const uint32_t *__restrict__ cell_frame,
+                                                       const Params *__restrict__ P, int which) {
+    if (P->status != kStatusOk) return;
+    const int64_t M = P->M;
+    if (which == 0 && M < kNearSplitBelow) return;
+    const bool batched = P->nframes > 1;
+    const int32_t giant_one = P->giant;
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    int64_t c0, c1;
+    list_chunk(M, c0, c1);
+    // kNgG groups of 256 cells per round, their parents loaded at once
+    constexpr int kNgG = 8;
     uint32_t mine = 0;
-    for (int64_t b0 = c0; b0 < c1; b0 += kBlock) {
-        const int64_t A = b0 + threadIdx.x;
-        const bool valid = A < c1;
-        const bool gi = valid && in_giant(A);
-        const uint64_t gm = __ballot(gi);
-        if (lane == 0 && valid) gbits[A >> 6] = gm;  // A is 64-aligned on lane 0
-        mine += (valid && !gi) ? 1u : 0u;
+    for (int64_t r0 = c0; r0 < c1; r0 += (int64_t)kNgG * kBlock) {
+        int32_t par[kNgG], fr[kNgG];
+#pragma unroll
+        for (int k = 0; k < kNgG; ++k) {
+            const int64_t A = r0 + k * kBlock + threadIdx.x;
+            par[k] = A < c1 ? cpar[A] : -1;
+            fr[k] = (A < c1 && batched) ? (int32_t)cell_frame[A] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kNgG; ++k) {
+            const int64_t A = r0 + k * kBlock + threadIdx.x;
+            const bool valid = A < c1;
+            const int32_t g = valid ? (batched ? frames[fr[k]].giant : giant_one) : -2;
+            const bool gi = valid && par[k] == g;
+            const uint64_t gm = __ballot(gi);
+            if (lane == 0 && valid) gbits[A >> 6] = gm;  // A is 64-aligned on lane 0
+            mine += (valid && !gi) ? 1u : 0u;
+        }
     }
+    __shared__ uint32_t s_w[kBlock / 64];
     mine = wave_sum(mine);
-    if (lane == 0) s_wcnt[wave] = mine;
+    if (lane == 0) s_w[wave] = mine;
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t tot = 0;
-        for (int i = 0; i < kBlock / 64; ++i) tot += s_wcnt[i];
-        s_base = tot ? atomicAdd(nwork, tot) : 0u;
+        for (int w = 0; w < kBlock / 64; ++w) tot += s_w[w];
+        listcnt[blockIdx.x] = tot;
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_work_list(const uint64_t *__restrict__ gbits,
+                                                      const uint32_t *__restrict__ listcnt,
+                                                      uint32_t *__restrict__ work,
+                                                      Params *__restrict__ P, int which) {
+    if (P->status != kStatusOk) return;
+    const int64_t M = P->M;
+    if (which == 0 && M < kNearSplitBelow) return;
+    __shared__ uint32_t s_tmp[kBlock / 64];
+    // where this block's cells go: the counts of the blocks before it (and
+    // block 0 publishes the total)
+    uint32_t before = 0, total = 0;
+    for (uint32_t b = threadIdx.x; b < gridDim.x; b += kBlock) {
+        const uint32_t c = listcnt[b];
+        before += b < blockIdx.x ? c : 0u;
+        total += c;
+    }
+    uint32_t t;
+    const uint32_t bsum = block_excl_scan(before, s_tmp, t);
+    (void)bsum;
+    const uint32_t base = t;  // sum of `before` over the block
     __syncthreads();
-    uint32_t base = s_base;
-    for (int64_t b0 = c0; b0 < c1; b0 += kBlock) {
-        const int64_t A = b0 + threadIdx.x;
-        const bool valid = A < c1;
-        const bool w = valid && !in_giant(A);
-        const uint64_t wm = __ballot(w);
-        if (lane == 0) s_wcnt[wave] = (uint32_t)__popcll(wm);
+    if (blockIdx.x == 0) {
+        const uint32_t x = block_excl_scan(total, s_tmp, t);
+        (void)x;
+        if (threadIdx.x == 0) *(which == 0 ? &P->nwork0 : &P->nwork) = t;
         __syncthreads();
-        uint32_t before = 0, tot = 0;
-#pragma unroll
-        for (int i = 0; i < kBlock / 64; ++i) {
-            before += i < wave ? s_wcnt[i] : 0u;
-            tot += s_wcnt[i];
+    }
+    int64_t c0, c1;
+    list_chunk(M, c0, c1);
+    // one 64-cell word of the bitmap per thread and step; listed cells are
+    // its zero bits below c1
+    uint32_t run = base;
+    for (int64_t w0 = c0 >> 6; w0 < (c1 + 63) >> 6; w0 += kBlock) {
+        const int64_t w = w0 + threadIdx.x;
+        uint64_t lst = 0;
+        if (w < (c1 + 63) >> 6) {
+            lst = ~gbits[w];
+            const int64_t hi = c1 - (w << 6);  // cells of this word below c1
+            if (hi < 64) lst &= (1ull << hi) - 1ull;
         }
-        if (w) work[base + before + (uint32_t)__popcll(wm & lanemask_lt())] = (uint32_t)A;
-        base += tot;
-        __syncthreads();
+        uint32_t tot;
+        const uint32_t off = block_excl_scan((uint32_t)__popcll(lst), s_tmp, tot);
+        uint32_t o = run + off;
+        while (lst) {
+            const int bit = __ffsll((unsigned long long)lst) - 1;
+            lst &= lst - 1ull;
+            work[o++] = (uint32_t)((w << 6) + bit);
+        }
+        run += tot;
+        __syncthreads();  // s_tmp is reused by the next step
     }
 }
 
@@ -2665,6 +2713,7 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     uint8_t *heads = reinterpret_cast<uint8_t *>(w + L.heads);
     int32_t *blkhead = reinterpret_cast<int32_t *>(w + L.blkhead);
     uint64_t *gbits = reinterpret_cast<uint64_t *>(w + L.gbits);
+    uint32_t *listcnt = reinterpret_cast<uint32_t *>(w + L.listcnt);
     uint32_t *work = reinterpret_cast<uint32_t *>(w + L.work);
     uint64_t *defer = reinterpret_cast<uint64_t *>(w + L.defer);
     uint32_t *cell_frame = nframes > 1 ? reinterpret_cast<uint32_t *>(w + L.cell_frame) : nullptr;
@@ -2687,6 +2736,7 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
         keys_pf = keys_pf < 1 ? 1 : keys_pf;
     }
     const int nb_finish = (nframes + kBlock - 1) / kBlock;
+    const int nb_list = nb_cells < kListBlocks ? nb_cells : kListBlocks;
     const int radix_bits = tn.radix_bits < kMinRadixBits
                                ? kMinRadixBits
                                : (tn.radix_bits > kMaxRadixBits ? kMaxRadixBits : tn.radix_bits);
@@ -2766,8 +2816,9 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
         FEC_LAUNCH(kStGiant0, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P, kNearSplitBelow));
         FEC_LAUNCH(kStGiant0, k_giant<<<(unsigned)nframes, 1024, 0, st>>>(cpar, frames, P,
                                                                           kNearSplitBelow));
-        FEC_LAUNCH(kStGiant0, k_nongiant<<<nb_cells, kBlock, 0, st>>>(cpar, gbits, work, frames,
-                                                                       cell_frame, P, 0));
+        FEC_LAUNCH(kStGiant0, k_giant_bits<<<nb_list, kBlock, 0, st>>>(cpar, gbits, listcnt, frames,
+                                                                        cell_frame, P, 0));
+        FEC_LAUNCH(kStGiant0, k_work_list<<<nb_list, kBlock, 0, st>>>(gbits, listcnt, work, P, 0));
         FEC_HOOK_NEAR_ALL(kNearWork, nb_cells);
     }
     FEC_HOOK_NEAR_ALL(kNearSplit, nb_cells);
@@ -2776,8 +2827,9 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
                                 L.defer_cap, 0));
     FEC_LAUNCH(kStCompress1, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P, 0));
     FEC_LAUNCH(kStGiant, k_giant<<<(unsigned)nframes, 1024, 0, st>>>(cpar, frames, P, 0));
-    FEC_LAUNCH(kStWorkList, k_nongiant<<<nb_cells, kBlock, 0, st>>>(cpar, gbits, work, frames,
-                                                                     cell_frame, P, 1));
+    FEC_LAUNCH(kStWorkList, k_giant_bits<<<nb_list, kBlock, 0, st>>>(cpar, gbits, listcnt, frames,
+                                                                      cell_frame, P, 1));
+    FEC_LAUNCH(kStWorkList, k_work_list<<<nb_list, kBlock, 0, st>>>(gbits, listcnt, work, P, 1));
     if (n >= (int64_t)kFarSplitBelow) {
         if (hook_block == 64) {
             FEC_HOOK_FAR(false, true, 64);

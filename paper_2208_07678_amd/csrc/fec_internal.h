@@ -11,6 +11,7 @@ namespace fec {
 constexpr int kBlock = 256;            // threads per block of the streaming kernels
 constexpr int kItems = 16;             // elements per thread in tiled kernels
 constexpr int kTile = kBlock * kItems; // elements per tile (sort, gather, cells)
+constexpr int kListBlocks = 1024;      // most blocks of the work-list kernels
 // Radix sort digits: 8 to 11 bits per pass, chosen per call on the host
 // (the autotuner's knob); tables are sized for the widest.
 constexpr int kMinRadixBits = 8;
@@ -106,7 +107,8 @@ struct Layout {
     size_t params, frames, partials, tile_cnt, tile_off;
     size_t keys0, keys1, vals0, vals1, th, dtot;
     size_t spts, sorig, cell_start, cell_key, cpar, csize, ccanon;
-    size_t col_key, col_cell, colgrid, colbits, heads, blkhead, gbits, work, cell_frame, defer;
+    size_t col_key, col_cell, colgrid, colbits, heads, blkhead, gbits, listcnt, work, cell_frame,
+        defer;
     uint64_t defer_cap;  // entries of the deferred-pair queue
     uint64_t colgrid_cap;
     size_t total;
@@ -172,6 +174,7 @@ constexpr Layout make_layout(int64_t n, int32_t nframes = 1) {
     L.heads = take(un);
     L.blkhead = take((size_t)L.ntiles * sizeof(int32_t));
     L.gbits = take((un / 64 + 1) * sizeof(uint64_t));
+    L.listcnt = take((size_t)kListBlocks * sizeof(uint32_t));
     L.work = take(un * sizeof(uint32_t));
     L.defer_cap = un / 2 + 1024;
     L.defer = take((size_t)L.defer_cap * sizeof(uint64_t));
