@@ -441,6 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ parti
     P->nwork = 0;
     P->nwork0 = 0;
     P->ndefer[0] = P->ndefer[1] = 0;
+    P->nrunq = 0;
     P->dense_cols = ((double)NX * (double)P->NYp <= (double)colgrid_cap) ? 1 : 0;
     P->hashed_cols = 0;
     uint64_t hcap = 1;
@@ -1416,11 +1417,13 @@ __device__ __forceinline__ void defer_test(uint64_t e, const float4 *__restrict_
 }
 
 // Runs: cell B = A + 1 (the next cell in key order) is often A's neighbour
-// one step up in z, or one step along y in the next column.  Such a pair is
-// tested; each cell that is not joined to its predecessor this way starts a
-// run.  Every cell of a run is connected to the run's first cell, which
-// becomes its parent: a valid union-find state (parent <= cell, same
-// component) reached without atomics.
+// one step up in z, or one step along y in the next column.  Such a pair's
+// first points are tested; each cell not joined to its predecessor this way
+// starts a run.  Every cell of a run is connected to the run's first cell,
+// which becomes its parent: a valid union-find state (parent <= cell, same
+// component) reached without atomics.  A pair whose first points are not
+// joined is queued and tested in full after the near shell (a full scan in
+// the runs pass held up its wave, and by then most such pairs share a root).
 __device__ __forceinline__ bool next_is_near(const Grid &g, uint64_t ka, uint64_t kb) {
     const uint64_t ca = ka >> g.bz, cb = kb >> g.bz;
     const int64_t za = (int64_t)(ka & g.zmask), zb = (int64_t)(kb & g.zmask);
@@ -1438,9 +1441,10 @@ __global__ __launch_bounds__(kBlock) void k_runs1(const float4 *__restrict__ spt
                                                   const uint64_t *__restrict__ cell_key,
                                                   uint8_t *__restrict__ heads,
                                                   int32_t *__restrict__ blkhead,
+                                                  uint32_t *__restrict__ runq,
                                                   const Frame *__restrict__ frames,
                                                   const uint32_t *__restrict__ cell_frame,
-                                                  const Params *__restrict__ P) {
+                                                  Params *__restrict__ P) {
     if (P->status != kStatusOk) return;
     const int64_t M = P->M;
     const int64_t base = (int64_t)blockIdx.x * kTile;
@@ -1449,6 +1453,8 @@ __global__ __launch_bounds__(kBlock) void k_runs1(const float4 *__restrict__ spt
     const bool batched = P->nframes > 1;
     const Grid g = grid_of(P);
     int32_t last = -1;
+    uint32_t qbits = 0;  // bit k: the pair ending at the thread's k-th cell is queued
+    static_assert(kItems <= 32, "queue flags are 32-bit");
     // kR cells per lane at a time, their loads issued in rounds (keys; cell
     // starts and thresholds; the first point of both cells), so that a lane
     // does not wait on one chain of dependent loads per cell in turn
@@ -1487,11 +1493,26 @@ __global__ __launch_bounds__(kBlock) void k_runs1(const float4 *__restrict__ spt
         for (int u = 0; u < kR; ++u) {
             if (!in[u]) continue;
             bool head = true;
-            if (nr[u])
-                head = !(joined(pa[u].x, pa[u].y, pa[u].z, pb[u], d2[u]) ||
-                         any_joined_1(spts, s0[u], s1[u], s1[u], s2[u], d2[u]));
+            if (nr[u]) {
+                head = !joined(pa[u].x, pa[u].y, pa[u].z, pb[u], d2[u]);
+                if (head) qbits |= 1u << (k0 + u);
+            }
             heads[A[u]] = head ? 1 : 0;
             if (head) last = (int32_t)A[u];
+        }
+    }
+    // the queued pairs: one reservation per block
+    {
+        __shared__ uint32_t s_tmp[kBlock / 64];
+        __shared__ uint32_t s_qbase;
+        uint32_t tot;
+        const uint32_t off = block_excl_scan((uint32_t)__popc(qbits), s_tmp, tot);
+        if (threadIdx.x == 0) s_qbase = tot ? atomicAdd(&P->nrunq, tot) : 0u;
+        __syncthreads();
+        uint32_t o = s_qbase + off;
+        for (uint32_t q = qbits; q; q &= q - 1u) {
+            const int k = __ffs(q) - 1;
+            runq[o++] = (uint32_t)(base + k * kBlock + threadIdx.x);
         }
     }
     // block max of the last run start
@@ -1928,14 +1949,23 @@ __global__ __launch_bounds__(kBlock) void k_deferred(const float4 *__restrict__ 
                                                      const uint32_t *__restrict__ cell_frame,
                                                      int32_t *cpar, const Params *__restrict__ P,
                                                      const uint64_t *__restrict__ defer,
-                                                     uint64_t defer_cap, int which) {
+                                                     uint64_t defer_cap,
+                                                     const uint32_t *__restrict__ runq, int which) {
     if (P->status != kStatusOk) return;
     const uint64_t cnt = P->ndefer[which] < defer_cap ? P->ndefer[which] : defer_cap;
+    // after the near shell, also the runs pass's pairs (cell A - 1, cell A)
+    const uint64_t nq = which == 0 ? P->nrunq : 0;
     const bool batched = P->nframes > 1;
     const float d2_one = P->d2;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < cnt;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < cnt + nq;
          i += (uint64_t)gridDim.x * kBlock) {
-        const uint64_t e = defer[i];
+        uint64_t e;
+        if (i < cnt) {
+            e = defer[i];
+        } else {
+            const uint32_t B = runq[i - cnt];
+            e = ((uint64_t)(B - 1u) << 32) | B;
+        }
         const int32_t A = (int32_t)(e >> 32);
         defer_test(e, spts, cell_start, cpar, batched ? frames[cell_frame[A]].d2 : d2_one);
     }
@@ -2716,6 +2746,7 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     uint32_t *listcnt = reinterpret_cast<uint32_t *>(w + L.listcnt);
     uint32_t *work = reinterpret_cast<uint32_t *>(w + L.work);
     uint64_t *defer = reinterpret_cast<uint64_t *>(w + L.defer);
+    uint32_t *runq = reinterpret_cast<uint32_t *>(w + L.runq);
     uint32_t *cell_frame = nframes > 1 ? reinterpret_cast<uint32_t *>(w + L.cell_frame) : nullptr;
 
     const int64_t ntiles = L.ntiles;
@@ -2781,7 +2812,8 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
                                                                    colgrid, colbits, P));
     // runs, near shell, giant component, far shell
     FEC_LAUNCH(kStRuns, k_runs1<<<(unsigned)ntiles, kBlock, 0, st>>>(
-                            spts, cell_start, cell_key, heads, blkhead, frames, cell_frame, P));
+                            spts, cell_start, cell_key, heads, blkhead, runq, frames, cell_frame,
+                            P));
     FEC_LAUNCH(kStRuns, k_runs2<<<(unsigned)ntiles, kBlock, 0, st>>>(heads, blkhead, cpar, P));
     // Each shell has large-table and small-table forms; which one a call
     // needs is known on the device only, so both are launched and the other
@@ -2824,7 +2856,7 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     FEC_HOOK_NEAR_ALL(kNearSplit, nb_cells);
     FEC_LAUNCH(kStDeferred, k_deferred<<<nb_cells, kBlock, 0, st>>>(
                                 spts, cell_start, frames, cell_frame, cpar, P, defer,
-                                L.defer_cap, 0));
+                                L.defer_cap, runq, 0));
     FEC_LAUNCH(kStCompress1, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P, 0));
     FEC_LAUNCH(kStGiant, k_giant<<<(unsigned)nframes, 1024, 0, st>>>(cpar, frames, P, 0));
     FEC_LAUNCH(kStWorkList, k_giant_bits<<<nb_list, kBlock, 0, st>>>(cpar, gbits, listcnt, frames,
@@ -2850,7 +2882,7 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
 #undef FEC_HOOK_FAR
     FEC_LAUNCH(kStDeferred, k_deferred<<<nb_cells, kBlock, 0, st>>>(
                                 spts, cell_start, frames, cell_frame, cpar, P, defer,
-                                L.defer_cap, 1));
+                                L.defer_cap, runq, 1));
     FEC_LAUNCH(kStCompress2, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P, 0));
     FEC_LAUNCH(kStFinalCells, k_final_cells<<<nb_cells, kBlock, 0, st>>>(
                                   cpar, cell_start, sorig, csize, ccanon, P));

@@ -90,6 +90,10 @@ struct Params {
     // Cell pairs whose first points are not joined, queued by the near and
     // the far shell for a full test once the shell's other joins are in.
     uint32_t ndefer[2];
+    // Consecutive cell pairs of the runs pass whose first points are not
+    // joined, tested after the near shell with the queued pairs above.
+    uint32_t nrunq;
+    uint32_t pad2;
     int32_t kept;         // kept clusters
     int32_t max_cell;     // largest number of points in one cell
     // Hashed column index (when the dense one does not fit): open addressing
@@ -108,7 +112,7 @@ struct Layout {
     size_t keys0, keys1, vals0, vals1, th, dtot;
     size_t spts, sorig, cell_start, cell_key, cpar, csize, ccanon;
     size_t col_key, col_cell, colgrid, colbits, heads, blkhead, gbits, listcnt, work, cell_frame,
-        defer;
+        defer, runq;
     uint64_t defer_cap;  // entries of the deferred-pair queue
     uint64_t colgrid_cap;
     size_t total;
@@ -178,6 +182,9 @@ constexpr Layout make_layout(int64_t n, int32_t nframes = 1) {
     L.work = take(un * sizeof(uint32_t));
     L.defer_cap = un / 2 + 1024;
     L.defer = take((size_t)L.defer_cap * sizeof(uint64_t));
+    // at most one pair per cell; in the memory of the sort's second index
+    // array, which nothing reads after the gather
+    L.runq = L.vals1;
     L.cell_frame = take(nframes > 1 ? un * sizeof(uint32_t) : 0);  // frame of every cell
     L.total = off;
     return L;
