@@ -1704,11 +1704,64 @@ __device__ __forceinline__ bool is_giant(const uint64_t *__restrict__ gbits, uin
     return (gbits[B >> 6] >> (B & 63)) & 1ull;
 }
 
+// Occupied columns of the (2H+1)x(2H+1) neighbourhood of column (cx, cy),
+// from the dense index's occupancy bits (one or two words per row): bit
+// (dx + H) * (2H + 1) + (dy + H).
+template <int H>
+__device__ __forceinline__ uint32_t occupied_box(const Grid &g, const uint32_t *__restrict__ colbits,
+                                                 int64_t cx, int64_t cy) {
+    constexpr int W = 2 * H + 1;
+    const int64_t y0 = cy - H < 0 ? 0 : cy - H;
+    const int64_t y1 = cy + H >= g.NY ? g.NY - 1 : cy + H;
+    uint32_t w0[W], w1[W];
+    int64_t i0[W];
+#pragma unroll
+    for (int r = 0; r < W; ++r) {
+        const int64_t x = cx + r - H;
+        const bool in = x >= 0 && x < g.NX;
+        i0[r] = in ? x * g.NYp + y0 : 0;
+        const int64_t i1 = in ? x * g.NYp + y1 : 0;
+        w0[r] = in ? colbits[i0[r] >> 5] : 0u;
+        w1[r] = in && (i1 >> 5) != (i0[r] >> 5) ? colbits[i1 >> 5] : 0u;
+    }
+    const uint32_t width = (uint32_t)(y1 - y0 + 1), lo = (uint32_t)(y0 - (cy - H));
+    uint32_t m = 0;
+#pragma unroll
+    for (int r = 0; r < W; ++r) {
+        const uint64_t two = ((uint64_t)w1[r] << 32) | w0[r];
+        const uint32_t row = (uint32_t)(two >> (i0[r] & 31)) & ((1u << width) - 1u);
+        m |= row << (r * W + lo);
+    }
+    return m;
+}
+
+// The 5x5 box as a 24-bit mask in the far shell's column order: bit q for
+// q' = (dx + 2) * 5 + (dy + 2), q = q' below the centre (q' = 12, left out)
+// and q' - 1 above.
+__device__ __forceinline__ uint32_t occupied_5x5(const Grid &g, const uint32_t *__restrict__ colbits,
+                                                 int64_t cx, int64_t cy) {
+    const uint32_t m = occupied_box<2>(g, colbits, cx, cy);
+    return (m & 0xFFFu) | ((m >> 1) & ~0xFFFu);
+}
+
+// The 3x3 box as an 8-bit mask in the near shell's column order: bits 0..3
+// the forward columns (0, +1), (1, -1), (1, 0), (1, +1), bits 4..7 the
+// backward ones (0, -1), (-1, +1), (-1, 0), (-1, -1).
+__device__ __forceinline__ uint32_t occupied_near(const Grid &g, const uint32_t *__restrict__ colbits,
+                                                  int64_t cx, int64_t cy) {
+    const uint32_t m = occupied_box<1>(g, colbits, cx, cy);  // bit (dx + 1) * 3 + (dy + 1)
+    auto b = [&](int dx, int dy) { return (m >> ((dx + 1) * 3 + (dy + 1))) & 1u; };
+    return b(0, 1) | b(1, -1) << 1 | b(1, 0) << 2 | b(1, 1) << 3 | b(0, -1) << 4 |
+           b(-1, 1) << 5 | b(-1, 0) << 6 | b(-1, -1) << 7;
+}
+
 // Forms of the near shell: every cell, one task per candidate column (small
 // cell tables); every cell, one task per cell (large tables); on large
 // tables of large clouds, the sampling links and then the full shell over
-// the cells outside their giant component.
-constexpr int kNearSplit = 0, kNearAll = 1, kNearSample = 2, kNearWork = 3;
+// the cells outside their giant component, with the dense column index on
+// the occupied columns only (kNearWorkOcc; its own instance, as for the far
+// shell), else on all eight.
+constexpr int kNearSplit = 0, kNearAll = 1, kNearSample = 2, kNearWork = 3, kNearWorkOcc = 4;
 // The sampling links go to the first cells of the three columns at dx = +1
 // (mask over near_col's columns): the column (0, +1) adds few links the runs
 // have not made already (map: sampling 0.65 ms and near shell 0.55 ms either
@@ -1747,9 +1800,11 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
     const int64_t M = P->M;
     constexpr bool kSplit = kMode == kNearSplit;
     constexpr bool kSample = kMode == kNearSample;
-    constexpr bool kWork = kMode == kNearWork;
+    constexpr bool kWork = kMode == kNearWork || kMode == kNearWorkOcc;
+    constexpr bool kOcc = kMode == kNearWorkOcc;
     if ((M < kNearSplitBelow) != kSplit) return;  // another form's case
     const ColIndex ci = colindex_of(P, colgrid, colbits, col_key, col_cell);
+    if (kWork && (ci.mode == kColDense) != kOcc) return;  // the other work-list form's case
     const float d2_one = P->d2;
     const bool batched = P->nframes > 1;
     const Grid g = grid_of(P);
@@ -1780,7 +1835,8 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
         const int task = (int)(t % kTasks);
         // round 1
         const uint64_t key = cell_key[A];
-        const uint32_t sA = cell_start[A], eA = cell_start[A + 1];
+        // (the sampling links test first points only: no point ranges)
+        const uint32_t sA = cell_start[A], eA = kSample ? 0u : cell_start[A + 1];
         const int32_t p0 = cpar[A];
         const uint32_t fA = batched ? cell_frame[A] : 0u;
         const uint64_t ck = key >> g.bz;
@@ -1791,12 +1847,16 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
         const int32_t q0 = cpar[p0];
         const float d2 = batched ? frames[fA].d2 : d2_one;  // neighbours share A's frame
         int32_t ra = -1;  // A's root, found once the first group's loads are out
+        // kOcc: the occupied columns, kNG at a time; otherwise fixed groups
+        uint32_t todo = kOcc ? occupied_near(g, colbits, cx, cy) : 0u;
 #pragma unroll 1
-        for (int grp = kSplit ? task : 0; grp < (kSplit ? task + 1 : kGroups); ++grp) {
-            const int o0 = grp * kNG;
-            // backward columns (work list): only pairs towards the giant
-            // component, the others are their other cell's forward pairs
-            const bool back = kWork && o0 >= 4;
+        for (int grp = kSplit ? task : 0;
+             kOcc ? todo != 0u : grp < (kSplit ? task + 1 : kGroups); ++grp) {
+            // column of each slot; backward columns (work list): only pairs
+            // towards the giant component, the others are their other
+            // cell's forward pairs
+            int qs[kNG];
+            bool back[kNG];
             // round 2: neighbour columns
             bool has[kNG];
             uint32_t fc[kNG];
@@ -1804,18 +1864,48 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
             int64_t nxs[kNG], nys[kNG];
 #pragma unroll
             for (int o = 0; o < kNG; ++o) {
+                const bool use = !kOcc || todo != 0u;
+                qs[o] = kOcc ? (use ? __ffs(todo) - 1 : 0) : grp * kNG + o;
+                if (kOcc) todo &= todo - 1u;
+                back[o] = kWork && qs[o] >= 4;
                 int dx, dy;
-                near_col((o0 + o) & 3, dx, dy);
-                if (back) {
+                near_col(qs[o] & 3, dx, dy);
+                if (back[o]) {
                     dx = -dx;
                     dy = -dy;
                 }
-                nxs[o] = cx + dx;
+                nxs[o] = use ? cx + dx : -1;  // an unused slot: off the grid
                 nys[o] = cy + dy;
-                want[o] = g.col_key((uint64_t)nxs[o], (uint64_t)nys[o]);
-                if (kSample && !((kSampleCols >> (o0 + o)) & 1u)) nxs[o] = -1;  // off the grid
+                want[o] = g.col_key((uint64_t)(cx + dx), (uint64_t)nys[o]);
+                if (kSample && !((kSampleCols >> qs[o]) & 1u)) nxs[o] = -1;  // off the grid
             }
-            find_columns<kNG>(g, ci, nxs, nys, has, fc);
+            if (kSample && ci.mode == kColDense) {
+                // the sampled columns lie in row cx + 1, at cy - 1 .. cy + 1:
+                // their occupancy bits come from one or two words
+                const bool rin = cx + 1 < g.NX;
+                const int64_t ylo = cy > 0 ? cy - 1 : 0;
+                const int64_t i0 = rin ? (cx + 1) * g.NYp + ylo : 0;
+                const int64_t i1 = rin ? (cx + 1) * g.NYp + (cy + 1 < g.NY ? cy + 1 : g.NY - 1) : 0;
+                const uint32_t w0 = rin ? ci.colbits[i0 >> 5] : 0u;
+                const uint32_t w1 = (rin && (i1 >> 5) != (i0 >> 5)) ? ci.colbits[i1 >> 5] : 0u;
+                const uint64_t two = ((uint64_t)w1 << 32) | w0;
+#pragma unroll
+                for (int o = 0; o < kNG; ++o) {
+                    const bool in = nxs[o] >= 0 && nxs[o] < g.NX && nys[o] >= 0 && nys[o] < g.NY;
+                    const int64_t idx = in ? nxs[o] * g.NYp + nys[o] : 0;
+                    has[o] = in && ((two >> (idx - (i0 & ~31ll))) & 1ull);
+                    fc[o] = has[o] ? ci.colgrid[idx] : 0u;
+                }
+            } else if (kOcc) {
+                // occupied by construction: only the first cells to load
+#pragma unroll
+                for (int o = 0; o < kNG; ++o) {
+                    has[o] = nxs[o] >= 0;
+                    fc[o] = has[o] ? ci.colgrid[(uint64_t)(nxs[o] * g.NYp + nys[o])] : 0u;
+                }
+            } else {
+                find_columns<kNG>(g, ci, nxs, nys, has, fc);
+            }
             // round 3: first cells of each column
             uint64_t kk[kNG][kNearK];
 #pragma unroll
@@ -1836,7 +1926,7 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
                     const bool inc = loaded && (kk[o][j] >> g.bz) == want[o];
                     const int64_t dz = (int64_t)(kk[o][j] & g.zmask) - cz;
                     bool c = inc && dz >= -1 && dz <= 1;
-                    if (back) c = c && is_giant(gbits, fc[o] + (uint32_t)j);
+                    if (back[o]) c = c && is_giant(gbits, fc[o] + (uint32_t)j);
                     if (c) cm |= 1u << (o * kNearK + j);
                     if (j == kNearK - 1 && inc && dz < 1) ovf |= 1u << o;
                 }
@@ -1844,8 +1934,12 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
             // column 0 is (0, +1): its first cell, when it is the next cell,
             // was decided by the runs pass; backwards, column (0, -1)'s cell
             // A - 1 likewise (its last cell, or its first when it has one)
-            if (o0 == 0 && fc[0] == (uint32_t)A + 1) cm &= ~1u;
-            if (back && fc[0] + (uint32_t)(kNearK - 1) == (uint32_t)A - 1) cm &= ~(1u << (kNearK - 1));
+#pragma unroll
+            for (int o = 0; o < kNG; ++o) {
+                if (qs[o] == 0 && fc[o] == (uint32_t)A + 1) cm &= ~(1u << (o * kNearK));
+                if (back[o] && qs[o] == 4 && fc[o] + (uint32_t)(kNearK - 1) == (uint32_t)A - 1)
+                    cm &= ~(1u << (o * kNearK + kNearK - 1));
+            }
             // round 4: parents and point ranges of the candidates
             int32_t rb[kCand];
             uint32_t sb[kCand], eb[kCand];
@@ -1855,7 +1949,7 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
                 const bool c = (cm >> i) & 1u;
                 rb[i] = c ? cpar[B] : -1;
                 sb[i] = c ? cell_start[B] : 0u;
-                eb[i] = c ? cell_start[B + 1] : 0u;
+                eb[i] = (c && !kSample) ? cell_start[B + 1] : 0u;
             }
             if (ra < 0) ra = (q0 == p0) ? p0 : uf_find(cpar, q0);
             FEC_COUNT(P, 0, __popc(cm));
@@ -1924,7 +2018,7 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
                         const int64_t dz = (int64_t)(kx[j] & g.zmask) - cz;
                         if (dz > 1) break;
                         if (dz < -1) continue;
-                        if (back && (B == (uint32_t)A - 1 || !is_giant(gbits, B))) continue;
+                        if (back[o] && (B == (uint32_t)A - 1 || !is_giant(gbits, B))) continue;
                         const int32_t r = uf_find(cpar, (int32_t)B);
                         if (r == ra) continue;
                         const uint32_t sB = cell_start[B];
@@ -2185,36 +2279,6 @@ __global__ __launch_bounds__(kBlock) void k_work_list(const uint64_t *__restrict
 // and dy > 0, or dx == dy == 0 and dz > 0) or the second cell is inside it.
 // So every far pair with at least one cell outside the giant component is
 // handled; pairs with both cells inside are already joined.
-
-// Occupied columns of the 5x5 neighbourhood of column (cx, cy), from the
-// dense index's occupancy bits (two words per row at most), as a 24-bit
-// mask in the far shell's column order: bit q for q' = (dx + 2) * 5 +
-// (dy + 2), q = q' below the centre (q' = 12, left out) and q' - 1 above.
-__device__ __forceinline__ uint32_t occupied_5x5(const Grid &g, const uint32_t *__restrict__ colbits,
-                                                 int64_t cx, int64_t cy) {
-    const int64_t y0 = cy - 2 < 0 ? 0 : cy - 2;
-    const int64_t y1 = cy + 2 >= g.NY ? g.NY - 1 : cy + 2;
-    uint32_t w0[5], w1[5];
-    int64_t i0[5];
-#pragma unroll
-    for (int r = 0; r < 5; ++r) {
-        const int64_t x = cx + r - 2;
-        const bool in = x >= 0 && x < g.NX;
-        i0[r] = in ? x * g.NYp + y0 : 0;
-        const int64_t i1 = in ? x * g.NYp + y1 : 0;
-        w0[r] = in ? colbits[i0[r] >> 5] : 0u;
-        w1[r] = in && (i1 >> 5) != (i0[r] >> 5) ? colbits[i1 >> 5] : 0u;
-    }
-    const uint32_t width = (uint32_t)(y1 - y0 + 1), lo = (uint32_t)(y0 - (cy - 2));
-    uint32_t m = 0;
-#pragma unroll
-    for (int r = 0; r < 5; ++r) {
-        const uint64_t two = ((uint64_t)w1[r] << 32) | w0[r];
-        const uint32_t row = (uint32_t)(two >> (i0[r] & 31)) & ((1u << width) - 1u);
-        m |= row << (r * 5 + lo);
-    }
-    return (m & 0xFFFu) | ((m >> 1) & ~0xFFFu);
-}
 
 // Work lists shorter than this are cut into one task per column group
 // (a small cloud leaves most of the chip idle, and each lane's chain of
@@ -2851,6 +2915,7 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
         FEC_LAUNCH(kStGiant0, k_giant_bits<<<nb_list, kBlock, 0, st>>>(cpar, gbits, listcnt, frames,
                                                                         cell_frame, P, 0));
         FEC_LAUNCH(kStGiant0, k_work_list<<<nb_list, kBlock, 0, st>>>(gbits, listcnt, work, P, 0));
+        FEC_HOOK_NEAR_ALL(kNearWorkOcc, nb_cells);
         FEC_HOOK_NEAR_ALL(kNearWork, nb_cells);
     }
     FEC_HOOK_NEAR_ALL(kNearSplit, nb_cells);
