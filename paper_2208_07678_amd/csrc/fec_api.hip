@@ -111,7 +111,8 @@ EventTimer g_timer;
 // on the current GPU comes from hipGetSymbolAddress, taken once per device
 // and kept.
 constexpr size_t kScratchBytes = FEC_NOALLOC_SCRATCH_BYTES;
-static_assert(fec::make_layout(FEC_NOALLOC_MAX_POINTS).total <= kScratchBytes,
+static_assert(fec::make_layout(FEC_NOALLOC_MAX_POINTS, 1, fec::kColGridPerPointNoAlloc).total <=
+                  kScratchBytes,
               "the scratch array holds the workspace of the largest call it admits");
 __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
@@ -221,7 +222,7 @@ int32_t fec_cluster_noalloc(const float *xyz, int64_t n, float d, int32_t min_si
     void *ws = nullptr;
     rc = scratch_address(&ws);
     if (rc != FEC_OK) return rc;
-    const fec::Layout L = fec::make_layout(n);
+    const fec::Layout L = fec::make_layout(n, 1, fec::kColGridPerPointNoAlloc);
     fec::CallArgs a{};
     a.xyz = xyz;
     a.n = n;

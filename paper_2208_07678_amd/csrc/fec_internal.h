@@ -22,8 +22,12 @@ constexpr int kDefaultRadixBits = 9;
 constexpr int kBboxBlocks = 1024;      // max blocks of the bounding-box reduction
 constexpr int kCellBlocks = 4096;      // grid of the grid-stride per-cell kernels
 // Dense column index: one entry per (cx, cy) when the plane has at most
-// kColGridPerPoint entries per point (else columns are binary-searched).
-constexpr int kColGridPerPoint = 8;
+// kColGridPerPoint entries per point (else hashed or binary-searched).  A
+// batch of single scans stacks its frames' planes along x and needs about
+// 11 (sized to the largest frame's width in y); the no-allocation entry
+// point keeps 8, to fit its static workspace.
+constexpr int kColGridPerPoint = 16;
+constexpr int kColGridPerPointNoAlloc = 8;
 // Frames of one batched call (each frame is an independent cloud).
 constexpr int32_t kMaxFrames = 65536;
 
@@ -139,7 +143,8 @@ constexpr int32_t bbox_blocks_per_frame(int64_t n, int32_t nframes) {
     return (int32_t)(b < 1 ? 1 : b);
 }
 
-constexpr Layout make_layout(int64_t n, int32_t nframes = 1) {
+constexpr Layout make_layout(int64_t n, int32_t nframes = 1,
+                             int col_per_point = kColGridPerPoint) {
     Layout L{};
     L.nframes = nframes;
     L.bbox_per_frame = bbox_blocks_per_frame(n, nframes);
@@ -172,7 +177,7 @@ constexpr Layout make_layout(int64_t n, int32_t nframes = 1) {
     L.ccanon = take(un * sizeof(int32_t));
     L.col_key = take(un * sizeof(uint64_t));
     L.col_cell = take((un + 1) * sizeof(uint32_t));
-    L.colgrid_cap = (uint64_t)kColGridPerPoint * un + 1024;
+    L.colgrid_cap = (uint64_t)col_per_point * un + 1024;
     L.colgrid = take((size_t)L.colgrid_cap * sizeof(uint32_t));
     L.colbits = take((size_t)(L.colgrid_cap / 32 + 2) * sizeof(uint32_t));
     L.heads = take(un);

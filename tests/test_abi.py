@@ -79,7 +79,10 @@ def test_host_side_argument_checks(fec):
 
 def test_noalloc_host_side_checks(fec):
     # the no-allocation form's size limit and argument checks come before
-    # any device call; its scratch array holds the largest call it admits
+    # any device call (that its scratch array holds the workspace of the
+    # largest call it admits is a static_assert of the library's build; that
+    # workspace keeps a smaller dense column index than fec_workspace_bytes
+    # sizes for the other entry points)
     lib = fec.raw_lib()
     buf = ctypes.c_void_p(0x1000)   # never dereferenced: checks fail first
     hdr = open(HEADER).read()
@@ -87,7 +90,7 @@ def test_noalloc_host_side_checks(fec):
     sb = re.search(r"#define FEC_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", hdr)
     scratch = int(sb.group(1)) << int(sb.group(2))
     assert lim == fec.NOALLOC_MAX_POINTS
-    assert 0 < fec.workspace_bytes(lim) <= scratch
+    assert 0 < lim * 64 <= scratch
     for n, d, mn, mx in [(lim + 1, 0.5, 1, 5), (-1, 0.5, 1, 5), (10, 0.0, 1, 5),
                          (10, float("nan"), 1, 5), (10, 0.5, 6, 5)]:
         rc = lib.fec_cluster_noalloc(buf, n, ctypes.c_float(d), mn, mx, buf, None, None)
