@@ -1758,10 +1758,11 @@ __device__ __forceinline__ uint32_t occupied_near(const Grid &g, const uint32_t 
 // Forms of the near shell: every cell, one task per candidate column (small
 // cell tables); every cell, one task per cell (large tables); on large
 // tables of large clouds, the sampling links and then the full shell over
-// the cells outside their giant component, with the dense column index on
-// the occupied columns only (kNearWorkOcc; its own instance, as for the far
-// shell), else on all eight.
-constexpr int kNearSplit = 0, kNearAll = 1, kNearSample = 2, kNearWork = 3, kNearWorkOcc = 4;
+// the cells outside their giant component.  With the dense column index the
+// one-task-per-cell forms visit the occupied columns only (kNearAllOcc,
+// kNearWorkOcc: instances of their own, as for the far shell).
+constexpr int kNearSplit = 0, kNearAll = 1, kNearSample = 2, kNearWork = 3, kNearWorkOcc = 4,
+              kNearAllOcc = 5;
 // The sampling links go to the first cells of the three columns at dx = +1
 // (mask over near_col's columns): the column (0, +1) adds few links the runs
 // have not made already (map: sampling 0.65 ms and near shell 0.55 ms either
@@ -1801,10 +1802,12 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
     constexpr bool kSplit = kMode == kNearSplit;
     constexpr bool kSample = kMode == kNearSample;
     constexpr bool kWork = kMode == kNearWork || kMode == kNearWorkOcc;
-    constexpr bool kOcc = kMode == kNearWorkOcc;
+    constexpr bool kOcc = kMode == kNearWorkOcc || kMode == kNearAllOcc;
+    constexpr bool kAll = kMode == kNearAll || kMode == kNearAllOcc;
     if ((M < kNearSplitBelow) != kSplit) return;  // another form's case
     const ColIndex ci = colindex_of(P, colgrid, colbits, col_key, col_cell);
-    if (kWork && (ci.mode == kColDense) != kOcc) return;  // the other work-list form's case
+    // the occupancy form of the pair, or the other
+    if ((kWork || kAll) && (ci.mode == kColDense) != kOcc) return;
     const float d2_one = P->d2;
     const bool batched = P->nframes > 1;
     const Grid g = grid_of(P);
@@ -1835,6 +1838,12 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
         const int task = (int)(t % kTasks);
         // round 1
         const uint64_t key = cell_key[A];
+        // the sampling links come from the first (lowest) cell of each
+        // column only: the cells above it mostly reach the same neighbour
+        // columns' first cells, and the runs join them to it where their
+        // points are joined (map: sampling 0.57 -> 0.50 ms, its work list
+        // 2.30 -> 2.36 M cells, call 3.77 -> 3.74 ms)
+        if (kSample && A > 0 && (cell_key[A - 1] >> g.bz) == (key >> g.bz)) continue;
         // (the sampling links test first points only: no point ranges)
         const uint32_t sA = cell_start[A], eA = kSample ? 0u : cell_start[A + 1];
         const int32_t p0 = cpar[A];
@@ -1848,7 +1857,7 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
         const float d2 = batched ? frames[fA].d2 : d2_one;  // neighbours share A's frame
         int32_t ra = -1;  // A's root, found once the first group's loads are out
         // kOcc: the occupied columns, kNG at a time; otherwise fixed groups
-        uint32_t todo = kOcc ? occupied_near(g, colbits, cx, cy) : 0u;
+        uint32_t todo = kOcc ? occupied_near(g, colbits, cx, cy) & (kWork ? 0xFFu : 0x0Fu) : 0u;
 #pragma unroll 1
         for (int grp = kSplit ? task : 0;
              kOcc ? todo != 0u : grp < (kSplit ? task + 1 : kGroups); ++grp) {
@@ -2904,7 +2913,10 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     const bool sampled =
         n >= kNearSplitBelow &&
         (tn.near_sampling == 1 || (tn.near_sampling == 0 && n / nframes >= kSampleMinPoints));
-    if (n >= kNearSplitBelow && !sampled) FEC_HOOK_NEAR_ALL(kNearAll, nb_cells);
+    if (n >= kNearSplitBelow && !sampled) {
+        FEC_HOOK_NEAR_ALL(kNearAllOcc, nb_cells);
+        FEC_HOOK_NEAR_ALL(kNearAll, nb_cells);
+    }
     if (sampled) {
         // sampling links, their giant component and work list, then the near
         // shell on that list
