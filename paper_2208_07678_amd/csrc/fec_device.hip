@@ -1816,7 +1816,10 @@ __global__ __launch_bounds__(BLK) void k_hook_near(const float4 *__restrict__ sp
     constexpr int kC = kWork ? 8 : 4;
     // columns per group: a group's loads are issued together, the groups of
     // a cell one after the other (fewer registers, more waves)
-    constexpr int kNG = kSplit ? 1 : kNearGroup;
+    // (the all-cell occupancy form: two at a time, for its four columns;
+    // 64-frame batch 0.245 -> 0.227 ms; the work-list form keeps four, the
+    // map's near shell being 0.60 -> 0.61 ms with two)
+    constexpr int kNG = kSplit ? 1 : (kMode == kNearAllOcc ? 2 : kNearGroup);
     constexpr int kGroups = kC / kNG;
     constexpr int kCand = kNG * kNearK;
     static_assert(kC % kNG == 0 && kCand <= 32, "groups cover the columns; 32-bit masks");
