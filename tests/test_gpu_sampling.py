@@ -98,3 +98,25 @@ def test_batch_with_sampling_matches_oracle():
             assert np.array_equal(gl, wl), "frame %d sampling %d: %s" % (
                 b, sampling, describe_mismatch(gl, wl))
             assert ks[b] == wk
+
+
+def test_large_forms_with_the_hash_index_match_oracle():
+    # small clumps over a 600 m square: about 30 plane entries per point, so
+    # the column index is the hash table, and more than 131,072 cells with
+    # no giant component, so both shells take their large forms without
+    # occupancy bits (and the near shell its sampled form when asked)
+    rng = np.random.default_rng(41)
+    c = rng.uniform(0, 600, size=(30000, 3)) * np.array([1, 1, 0.02])
+    xyz = (np.repeat(c, 10, axis=0) + rng.normal(0, 0.25, (300000, 3))).astype(np.float32)
+    d, mn, mx = 0.35, 2, 300000
+    want, wk = oracle.fec(xyz, d, mn, mx)
+    for sampling in (2, 1):
+        say("hash-index clumps, near_sampling", sampling)
+        got, k, st = _cluster(xyz, d, mn, mx, sampling)
+        say("stats", {k_: st[k_] for k_ in ("cells", "near_work_cells", "work_cells",
+                                          "column_index")})
+        assert st["column_index"] == 2 and st["cells"] >= 131072
+        assert st["work_cells"] >= 131072   # the far shell's large form
+        assert (st["near_work_cells"] > 0) == (sampling == 1)
+        assert np.array_equal(got, want), "sampling %d: %s" % (sampling, describe_mismatch(got, want))
+        assert k == wk
