@@ -598,8 +598,6 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(const uint64_t *__restrict
     if (pass >= P->npasses || P->status != kStatusOk) return;
     __shared__ uint32_t s_cnt[kBlock / 64][R];
     const int tid = threadIdx.x, wave = tid >> 6, lane = __lane_id();
-    for (int i = tid; i < (kBlock / 64) * R; i += kBlock) (&s_cnt[0][0])[i] = 0;
-    __syncthreads();
     // tiles by XCD eighths: neighbouring tiles write neighbouring words of
     // each digit's row of counts, which their XCD's L2 then merges into
     // whole lines (4-byte writes from tiles on different XCDs would each
@@ -607,12 +605,15 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(const uint64_t *__restrict
     const int64_t tile = xcd_block_eighths();
     const int shift = P->key_shift + pass * RB;
     const int64_t base = tile * kTile + (int64_t)wave * (64 * kItems);
+    // the tile's words first, their loads overlapping the counters' reset
     uint64_t v[kItems];
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const int64_t e = base + k * 64 + lane;
         v[k] = e < n ? src[e] : 0ull;
     }
+    for (int i = tid; i < (kBlock / 64) * R; i += kBlock) (&s_cnt[0][0])[i] = 0;
+    __syncthreads();
     // counts only (no ranks): one LDS atomic add per word, into the wave's
     // own row; lanes adding to one counter are serialised by the LDS, which
     // still costs far less than the ballots of a stable rank
