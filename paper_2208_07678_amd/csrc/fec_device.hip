@@ -2583,9 +2583,12 @@ __global__ __launch_bounds__(kBlock) void k_final_cells(const int32_t *__restric
 // caller's array (the sorted order is unrelated to the input's), where each
 // costs a partial line, so on clouds whose points mostly end in filtered
 // clusters the pass saves most of the label traffic.
+// Every label -1: the labels of the clusters the size filter drops, and on
+// a refused call (a status other than ok; no later kernel changes it) all
+// of them.
 __global__ __launch_bounds__(kBlock) void k_labels_clear(int32_t *__restrict__ labels, int64_t n,
                                                          const Params *__restrict__ P) {
-    if (P->status != kStatusOk) return;
+    (void)P;
     int4 *l4 = reinterpret_cast<int4 *>(labels);
     const int64_t n4 = ((uintptr_t)labels & 15) == 0 ? n / 4 : 0;
     const int4 m1 = make_int4(-1, -1, -1, -1);
@@ -2597,9 +2600,16 @@ __global__ __launch_bounds__(kBlock) void k_labels_clear(int32_t *__restrict__ l
         labels[i] = -1;
 }
 
+// Clouds below this many points write all their labels in one kernel.
+constexpr int64_t kLabelsAllBelow = 131072;
+
 // Labels in the caller's order and the number of kept clusters.  With
 // several frames, each cell takes its frame's size bounds, its label counts
 // from the frame's first point, and kept clusters are counted per frame.
+// Only kept clusters' labels are written after k_labels_clear; with
+// `write_all` (small clouds, where one launch fewer matters more than the
+// scattered writes of the -1 labels) every label is, -1 included, and a
+// refused call fills them all with -1 here.
 __global__ __launch_bounds__(kBlock) void k_final_labels(const int32_t *__restrict__ cpar,
                                                          const uint32_t *__restrict__ cell_start,
                                                          const uint32_t *__restrict__ sorig,
@@ -2608,8 +2618,14 @@ __global__ __launch_bounds__(kBlock) void k_final_labels(const int32_t *__restri
                                                          int32_t *__restrict__ labels,
                                                          Frame *__restrict__ frames,
                                                          const uint32_t *__restrict__ cell_frame,
-                                                         Params *__restrict__ P) {
-    if (P->status != kStatusOk) return;
+                                                         Params *__restrict__ P, int write_all) {
+    if (P->status != kStatusOk) {
+        if (write_all)
+            for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < P->n;
+                 i += (int64_t)gridDim.x * kBlock)
+                labels[i] = -1;
+        return;
+    }
     const int64_t M = P->M;
     const int nframes = P->nframes;
     const bool batched = nframes > 1;
@@ -2646,7 +2662,7 @@ __global__ __launch_bounds__(kBlock) void k_final_labels(const int32_t *__restri
                 }
             }
         }
-        if (!ok) continue;  // -1 is there already (k_labels_clear)
+        if (!ok && !write_all) continue;  // -1 is there already (k_labels_clear)
         const uint32_t s = cell_start[A], e = cell_start[A + 1];
         for (uint32_t p = s; p < e; p += 4) {  // four loads in flight
             uint32_t o[4];
@@ -2676,6 +2692,7 @@ __global__ __launch_bounds__(kBlock) void k_final_labels(const int32_t *__restri
         }
         const bool one_ok = accepted && lo <= 1u && 1u <= hi;
         if (one_ok) labels[o] = (int32_t)o - base;
+        else if (write_all) labels[o] = -1;
         if (!batched) kept += one_ok ? 1u : 0u;
         else if (one_ok) atomicAdd(&frames[f].kept, 1);
     }
@@ -2687,15 +2704,6 @@ __global__ __launch_bounds__(kBlock) void k_final_labels(const int32_t *__restri
     if (lane == 0 && kept) atomicAdd(&s_k, kept);
     __syncthreads();
     if (threadIdx.x == 0 && s_k) atomicAdd(&P->kept, (int32_t)s_k);
-}
-
-// On a device-side failure every label is -1.
-__global__ __launch_bounds__(kBlock) void k_error_fill(int32_t *__restrict__ labels, int64_t n,
-                                                       const Params *__restrict__ P) {
-    if (P->status == kStatusOk) return;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock)
-        labels[i] = -1;
 }
 
 // The count of an empty call (nothing else to enqueue).
@@ -2967,11 +2975,13 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     FEC_LAUNCH(kStCompress2, k_compress<<<nb_cells, kBlock, 0, st>>>(cpar, P, 0));
     FEC_LAUNCH(kStFinalCells, k_final_cells<<<nb_cells, kBlock, 0, st>>>(
                                   cpar, cell_start, sorig, csize, ccanon, P));
-    FEC_LAUNCH(kStFinalLabels, k_labels_clear<<<nb_stream, kBlock, 0, st>>>(labels_out, n, P));
+    // small clouds: one label kernel that writes every label
+    const int labels_all = n < kLabelsAllBelow ? 1 : 0;
+    if (!labels_all)
+        FEC_LAUNCH(kStFinalLabels, k_labels_clear<<<nb_stream, kBlock, 0, st>>>(labels_out, n, P));
     FEC_LAUNCH(kStFinalLabels, k_final_labels<<<nb_cells, kBlock, 0, st>>>(
                                    cpar, cell_start, sorig, csize, ccanon, labels_out, frames,
-                                   cell_frame, P));
-    FEC_LAUNCH(kStFinish, k_error_fill<<<nb_stream, kBlock, 0, st>>>(labels_out, n, P));
+                                   cell_frame, P, labels_all));
     FEC_LAUNCH(kStFinish, k_finish<<<(unsigned)nb_finish, kBlock, 0, st>>>(P, frames, nframes,
                                                                            args.k_out));
 #undef FEC_LAUNCH
