@@ -2586,9 +2586,7 @@ __global__ __launch_bounds__(kBlock) void k_final_cells(const int32_t *__restric
 // Every label -1: the labels of the clusters the size filter drops, and on
 // a refused call (a status other than ok; no later kernel changes it) all
 // of them.
-__global__ __launch_bounds__(kBlock) void k_labels_clear(int32_t *__restrict__ labels, int64_t n,
-                                                         const Params *__restrict__ P) {
-    (void)P;
+__global__ __launch_bounds__(kBlock) void k_labels_clear(int32_t *__restrict__ labels, int64_t n) {
     int4 *l4 = reinterpret_cast<int4 *>(labels);
     const int64_t n4 = ((uintptr_t)labels & 15) == 0 ? n / 4 : 0;
     const int4 m1 = make_int4(-1, -1, -1, -1);
@@ -2978,7 +2976,7 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
     // small clouds: one label kernel that writes every label
     const int labels_all = n < kLabelsAllBelow ? 1 : 0;
     if (!labels_all)
-        FEC_LAUNCH(kStFinalLabels, k_labels_clear<<<nb_stream, kBlock, 0, st>>>(labels_out, n, P));
+        FEC_LAUNCH(kStFinalLabels, k_labels_clear<<<nb_stream, kBlock, 0, st>>>(labels_out, n));
     FEC_LAUNCH(kStFinalLabels, k_final_labels<<<nb_cells, kBlock, 0, st>>>(
                                    cpar, cell_start, sorig, csize, ccanon, labels_out, frames,
                                    cell_frame, P, labels_all));
