@@ -1260,11 +1260,13 @@ __device__ __forceinline__ void find_columns(const Grid &g, const ColIndex &ci,
 // shell 1.04 -> 0.98 ms with groups of 8 columns; with one cell per column,
 // C = 128 for the near shell measures 1.68 -> 1.63 ms against C = 64, and
 // the far shell is the same for C from 8 to 64), batches of frames
-// unchanged.  The far shell's work list is sparse in the cells and gains
-// less; whole eighths per XCD (C = gridDim.x / 8) unbalance both shells on
-// batches (near 0.44 -> 0.64 ms).
+// unchanged.  Whole eighths per XCD (C = gridDim.x / 8) unbalance both
+// shells on batches (near 0.44 -> 0.64 ms).  The kernels over a work list
+// (far shell, near shell after the sampling links) take kXcdRunFar: with
+// the lists in cell order, C = 64 is best on the map (far shell 0.477 ->
+// 0.460 ms against 16; 32 and 128 in between), batches unchanged.
 constexpr uint32_t kXcdRunNear = 128;
-constexpr uint32_t kXcdRunFar = 16;
+constexpr uint32_t kXcdRunFar = 64;
 
 // Union-find over cells.  Two roots are joined by hooking the one of higher
 // rank under the other, rank being a fixed bijective scramble of the cell
