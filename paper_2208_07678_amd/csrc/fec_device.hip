@@ -588,11 +588,11 @@ __device__ __forceinline__ void block_excl_scan_multi(uint32_t (&v)[DPT], uint32
     }
 }
 
-// (1) per-tile digit counts, stored digit-major: th[dg * ntiles + tile].
+// (1) per-tile digit counts, stored digit-major: th[dg * pitch + tile].
 template <int RB>
 __global__ __launch_bounds__(kBlock) void k_sort_hist(const uint64_t *__restrict__ src,
                                                       const Params *__restrict__ P, int pass,
-                                                      int64_t n, int64_t ntiles,
+                                                      int64_t n, int64_t pitch,
                                                       uint32_t *__restrict__ th) {
     constexpr int R = 1 << RB, DPT = R / kBlock;
     if (pass >= P->npasses || P->status != kStatusOk) return;
@@ -630,15 +630,20 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(const uint64_t *__restrict
         uint32_t c = 0;
 #pragma unroll
         for (int w = 0; w < kBlock / 64; ++w) c += s_cnt[w][dg];
-        th[(int64_t)dg * ntiles + tile] = c;
+        th[(int64_t)dg * pitch + tile] = c;
     }
 }
 
 // (2) one block per digit: exclusive scan of the digit's per-tile counts
 // (positions relative to the digit's first word) and the digit's total,
 // published for the scatter blocks, which add the digits' bases themselves.
+// A thread takes kScanItems consecutive counts in 16-byte loads (rows start
+// on 16-byte boundaries, the table's pitch is a multiple of 4), so a round
+// covers 8,192 tiles (33.5 M words) and the map's table takes one.
+constexpr int kScanItems = 32;
 __global__ __launch_bounds__(kBlock) void k_sort_scan(const Params *__restrict__ P, int pass,
-                                                      int64_t ntiles, uint32_t *__restrict__ th,
+                                                      int64_t ntiles, int64_t pitch,
+                                                      uint32_t *__restrict__ th,
                                                       uint32_t *__restrict__ dtot) {
     if (pass >= P->npasses || P->status != kStatusOk) return;
     __shared__ uint32_t s_tmp[kBlock / 64];
@@ -647,25 +652,36 @@ __global__ __launch_bounds__(kBlock) void k_sort_scan(const Params *__restrict__
     uint32_t tot;
     if (tid == 0) s_carry = 0;
     __syncthreads();
-    uint32_t *row = th + (int64_t)d * ntiles;
-    for (int64_t c0 = 0; c0 < ntiles; c0 += kTile) {
-        // kItems consecutive counts per thread
-        uint32_t v[kItems], sum = 0;
+    uint32_t *row = th + (int64_t)d * pitch;
+    for (int64_t c0 = 0; c0 < ntiles; c0 += (int64_t)kBlock * kScanItems) {
+        // i0 is a multiple of 4: a group of 4 that starts below ntiles ends
+        // within the row's pitch; counts past ntiles are taken as 0
+        const int64_t i0 = c0 + (int64_t)tid * kScanItems;
+        uint32_t v[kScanItems], sum = 0;
 #pragma unroll
-        for (int k = 0; k < kItems; ++k) {
-            const int64_t i = c0 + (int64_t)tid * kItems + k;
-            v[k] = i < ntiles ? row[i] : 0u;
-            sum += v[k];
+        for (int k = 0; k < kScanItems; k += 4) {
+            uint4 q = make_uint4(0u, 0u, 0u, 0u);
+            if (i0 + k < ntiles) q = *reinterpret_cast<const uint4 *>(row + i0 + k);
+            v[k] = q.x;
+            v[k + 1] = i0 + k + 1 < ntiles ? q.y : 0u;
+            v[k + 2] = i0 + k + 2 < ntiles ? q.z : 0u;
+            v[k + 3] = i0 + k + 3 < ntiles ? q.w : 0u;
+            sum += v[k] + v[k + 1] + v[k + 2] + v[k + 3];
         }
         const uint32_t carry = s_carry;
         __syncthreads();
         const uint32_t before = block_excl_scan(sum, s_tmp, tot);
         uint32_t run = carry + before;
 #pragma unroll
-        for (int k = 0; k < kItems; ++k) {
-            const int64_t i = c0 + (int64_t)tid * kItems + k;
-            if (i < ntiles) row[i] = run;
-            run += v[k];
+        for (int k = 0; k < kScanItems; k += 4) {
+            uint4 q;
+            q.x = run;
+            q.y = q.x + v[k];
+            q.z = q.y + v[k + 1];
+            q.w = q.z + v[k + 2];
+            run = q.w + v[k + 3];
+            // positions past ntiles land in the row's padding, read by no one
+            if (i0 + k < ntiles) *reinterpret_cast<uint4 *>(row + i0 + k) = q;
         }
         __syncthreads();
         if (tid == 0) s_carry = carry + tot;
@@ -684,7 +700,7 @@ template <int RB>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(scatter_waves(RB)))) void
 k_sort_scatter(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
                const uint32_t *__restrict__ srcv, uint32_t *__restrict__ dstv,
-               const Params *__restrict__ P, int pass, int64_t n, int64_t ntiles,
+               const Params *__restrict__ P, int pass, int64_t n, int64_t pitch,
                const uint32_t *__restrict__ th, const uint32_t *__restrict__ dtot) {
     constexpr int R = 1 << RB, DPT = R / kBlock;
     if (pass >= P->npasses || P->status != kStatusOk) return;
@@ -721,7 +737,7 @@ k_sort_scatter(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
         block_excl_scan_multi<DPT>(tv, s_tmp, tot);
 #pragma unroll
         for (int q = 0; q < DPT; ++q)
-            s_base[tid * DPT + q] = tv[q] + th[(int64_t)(tid * DPT + q) * ntiles + tile];
+            s_base[tid * DPT + q] = tv[q] + th[(int64_t)(tid * DPT + q) * pitch + tile];
     }
     __syncthreads();
     uint32_t rk[kItems];
@@ -2782,6 +2798,7 @@ static hipError_t launch_sort(uint64_t *keys0, uint64_t *keys1, uint32_t *vals0,
                               const Params *P, int64_t n, int64_t ntiles, uint32_t *th,
                               uint32_t *dtot, hipStream_t st, Timer *timer) {
     constexpr int kPasses = (64 + RB - 1) / RB;
+    const int64_t pitch = tile_pitch(ntiles);
     for (int pass = 0; pass < kPasses; ++pass) {
         const uint64_t *src = (pass & 1) ? keys1 : keys0;
         uint64_t *dst = (pass & 1) ? keys0 : keys1;
@@ -2789,16 +2806,16 @@ static hipError_t launch_sort(uint64_t *keys0, uint64_t *keys1, uint32_t *vals0,
         uint32_t *dstv = (pass & 1) ? vals0 : vals1;
         hipError_t e;
         if (timer) timer->begin(kStSortHist, st);
-        k_sort_hist<RB><<<(unsigned)ntiles, kBlock, 0, st>>>(src, P, pass, n, ntiles, th);
+        k_sort_hist<RB><<<(unsigned)ntiles, kBlock, 0, st>>>(src, P, pass, n, pitch, th);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (timer) timer->end(kStSortHist, st);
         if (timer) timer->begin(kStSortScan, st);
-        k_sort_scan<<<1u << RB, kBlock, 0, st>>>(P, pass, ntiles, th, dtot);
+        k_sort_scan<<<1u << RB, kBlock, 0, st>>>(P, pass, ntiles, pitch, th, dtot);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (timer) timer->end(kStSortScan, st);
         if (timer) timer->begin(kStSort, st);
         k_sort_scatter<RB><<<(unsigned)ntiles, kBlock, 0, st>>>(src, dst, srcv, dstv, P, pass, n,
-                                                              ntiles, th, dtot);
+                                                              pitch, th, dtot);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (timer) timer->end(kStSort, st);
     }

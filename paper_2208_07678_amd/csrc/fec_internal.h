@@ -11,6 +11,9 @@ namespace fec {
 constexpr int kBlock = 256;            // threads per block of the streaming kernels
 constexpr int kItems = 16;             // elements per thread in tiled kernels
 constexpr int kTile = kBlock * kItems; // elements per tile (sort, gather, cells)
+// Row pitch of the sort's per-tile tables: the tile count rounded up to a
+// multiple of 4, so that every row starts on a 16-byte boundary.
+constexpr int64_t tile_pitch(int64_t ntiles) { return (ntiles + 3) & ~(int64_t)3; }
 constexpr int kListBlocks = 1024;      // most blocks of the work-list kernels
 // Radix sort digits: 8 to 11 bits per pass, chosen per call on the host
 // (the autotuner's knob); tables are sized for the widest.
@@ -166,7 +169,7 @@ constexpr Layout make_layout(int64_t n, int32_t nframes = 1,
     L.keys1 = take(un * sizeof(uint64_t));
     L.vals0 = take(un * sizeof(uint32_t));
     L.vals1 = take(un * sizeof(uint32_t));
-    L.th = take((size_t)L.ntiles * kMaxRadix * sizeof(uint32_t));
+    L.th = take((size_t)tile_pitch(L.ntiles) * kMaxRadix * sizeof(uint32_t));
     L.dtot = take((size_t)kMaxPasses * kMaxRadix * sizeof(uint32_t));
     L.spts = take(un * sizeof(float4));
     L.sorig = take(un * sizeof(uint32_t));
