@@ -289,7 +289,8 @@ int32_t fec_stage_count(void);
  * calls enqueued afterwards):
  *   cell_blocks    the most blocks of the per-cell grid-stride kernels
  *                  (default 4096), in [0, 2^20];
- *   stream_blocks  the most blocks of the per-point streaming kernels
+ *   stream_blocks  the most blocks of the per-point streaming kernel that
+ *                  sets every label to -1 before the kept clusters' labels
  *                  (default 4096), in [0, 2^20];
  *   radix_bits     bits per radix-sort pass: 8, 9, 10 or 11 (default 9);
  *                  wider digits take fewer passes over larger tables;

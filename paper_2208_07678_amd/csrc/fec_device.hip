@@ -146,6 +146,17 @@ __device__ __forceinline__ void frame_range(const int64_t *offs, int64_t n, int 
     hi = b;
 }
 
+// Frame holding original point index i: the last frame with off0 <= i.
+__device__ __forceinline__ int frame_of_point(const Frame *frames, int nframes, int64_t i) {
+    int lo = 0, hi = nframes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (frames[mid].off0 <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Per-block min/max of the finite points of one frame and their count;
 // block f * per_frame + j takes the j-th share of frame f.
 __global__ __launch_bounds__(kBlock) void k_bbox(const float *__restrict__ xyz, int64_t n,
@@ -473,47 +484,6 @@ __device__ __forceinline__ uint64_t make_key(uint64_t cx, uint64_t cy, uint64_t 
     return (((cx << by) | cy) << bz) | cz;
 }
 
-// ------------------------------------------------------------- 3. keys
-// Packs (cell key << idx_bits) | point index.  Block f * per_frame + j takes
-// the j-th share of frame f; the cell's x coordinate is offset by the
-// frame's place in the stacked grid.  Points of a refused frame get the key
-// of non-finite points (sorted last).
-__global__ __launch_bounds__(kBlock) void k_keys(const float *__restrict__ xyz,
-                                                 Params *__restrict__ P,
-                                                 const Frame *__restrict__ frames, int per_frame,
-                                                 uint64_t *__restrict__ keys,
-                                                 uint32_t *__restrict__ vals) {
-    if (P->status != kStatusOk) return;
-    const int f = blockIdx.x / per_frame, j = blockIdx.x % per_frame;
-    const Frame *F = frames + f;
-    const int64_t lo = F->off0, hi = F->off1;
-    const bool accepted = F->status == kStatusOk;
-    const int ks = P->key_shift;
-    const bool pair = P->pair_mode != 0;
-    const double ox = F->ox, oy = F->oy, oz = F->oz, inv = F->inv_s;
-    const int64_t NX = F->NX, NY = F->NY, NZ = F->NZ, xoff = F->xoff;
-    const int by = P->by, bz = P->bz;
-    const uint64_t invalid_key = 1ull << (P->bx + by + bz);
-    for (int64_t i = lo + (int64_t)j * kBlock + threadIdx.x; i < hi;
-         i += (int64_t)per_frame * kBlock) {
-        const float x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
-        uint64_t key;
-        if (accepted && finite3(x, y, z)) {
-            int64_t cx = (int64_t)floor(((double)x - ox) * inv);
-            int64_t cy = (int64_t)floor(((double)y - oy) * inv);
-            int64_t cz = (int64_t)floor(((double)z - oz) * inv);
-            cx = cx < 0 ? 0 : (cx >= NX ? NX - 1 : cx);
-            cy = cy < 0 ? 0 : (cy >= NY ? NY - 1 : cy);
-            cz = cz < 0 ? 0 : (cz >= NZ ? NZ - 1 : cz);
-            key = make_key((uint64_t)(xoff + cx), (uint64_t)cy, (uint64_t)cz, by, bz);
-        } else {
-            key = invalid_key;
-        }
-        keys[i] = pair ? key : ((key << ks) | (uint64_t)i);
-        if (pair) vals[i] = (uint32_t)i;
-    }
-}
-
 // Blocks go to the 8 XCDs round-robin by block id, and each XCD has its own
 // L2.  xcd_block<C>() renumbers the blocks so that each XCD runs runs of C
 // consecutive block numbers: in every whole group of 8C blocks, XCD x takes
@@ -540,6 +510,95 @@ __device__ __forceinline__ int64_t xcd_block_eighths() {
     const uint32_t g = gridDim.x, b = blockIdx.x, C = g / kXcds;
     if (C <= 1 || b >= kXcds * C) return b;
     return (int64_t)(b % kXcds) * C + b / kXcds;
+}
+
+// ------------------------------------------------------------- 3. keys
+// Packs (cell key << idx_bits) | point index, or the key alone with the
+// index in vals[] in pair mode; the cell's x coordinate is offset by the
+// frame's place in the stacked grid, and points of a refused frame get the
+// key of non-finite points (sorted last).  Each block takes one of the
+// sort's tiles of kTile points, numbered as the sort numbers them, and also
+// counts the first radix pass's digits of its words, stored as the sort's
+// histogram kernel stores them (th[dg * pitch + tile]): the first pass then
+// needs no histogram launch, nor a second read of the words.  Frames are
+// consecutive ranges of the points: a lane finds the frame of its first
+// point and walks on from there.
+template <int RB>
+__global__ __launch_bounds__(kBlock) void k_keys(const float *__restrict__ xyz,
+                                                 const Params *__restrict__ P,
+                                                 const Frame *__restrict__ frames, int nframes,
+                                                 int64_t n, int64_t pitch,
+                                                 uint64_t *__restrict__ keys,
+                                                 uint32_t *__restrict__ vals,
+                                                 uint32_t *__restrict__ th) {
+    constexpr int R = 1 << RB, DPT = R / kBlock;
+    if (P->status != kStatusOk) return;
+    __shared__ uint32_t s_cnt[kBlock / 64][R];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = __lane_id();
+    const int64_t tile = xcd_block_eighths();
+    const int64_t base = tile * kTile + (int64_t)wave * (64 * kItems);
+    for (int i = tid; i < (kBlock / 64) * R; i += kBlock) (&s_cnt[0][0])[i] = 0;
+    const int ks = P->key_shift;
+    const bool pair = P->pair_mode != 0;
+    const int by = P->by, bz = P->bz;
+    const uint64_t invalid_key = 1ull << (P->bx + by + bz);
+    // the lane's frame: range end, acceptance, origin, scale, extent, x offset
+    int f = 0;
+    if (nframes > 1 && base + lane < n) f = frame_of_point(frames, nframes, base + lane);
+    int64_t hi, NX, NY, NZ, xoff;
+    double ox, oy, oz, inv;
+    bool accepted;
+    auto load_frame = [&]() {
+        const Frame *F = frames + f;
+        hi = F->off1;
+        accepted = F->status == kStatusOk;
+        ox = F->ox;
+        oy = F->oy;
+        oz = F->oz;
+        inv = F->inv_s;
+        NX = F->NX;
+        NY = F->NY;
+        NZ = F->NZ;
+        xoff = F->xoff;
+    };
+    load_frame();
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < kItems; ++k) {
+        const int64_t e = base + k * 64 + lane;
+        if (e < n) {
+            while (e >= hi && f + 1 < nframes) {
+                ++f;
+                load_frame();
+            }
+            const float x = xyz[3 * e], y = xyz[3 * e + 1], z = xyz[3 * e + 2];
+            uint64_t key;
+            if (accepted && finite3(x, y, z)) {
+                int64_t cx = (int64_t)floor(((double)x - ox) * inv);
+                int64_t cy = (int64_t)floor(((double)y - oy) * inv);
+                int64_t cz = (int64_t)floor(((double)z - oz) * inv);
+                cx = cx < 0 ? 0 : (cx >= NX ? NX - 1 : cx);
+                cy = cy < 0 ? 0 : (cy >= NY ? NY - 1 : cy);
+                cz = cz < 0 ? 0 : (cz >= NZ ? NZ - 1 : cz);
+                key = make_key((uint64_t)(xoff + cx), (uint64_t)cy, (uint64_t)cz, by, bz);
+            } else {
+                key = invalid_key;
+            }
+            const uint64_t word = pair ? key : ((key << ks) | (uint64_t)e);
+            keys[e] = word;
+            if (pair) vals[e] = (uint32_t)e;
+            atomicAdd(&s_cnt[wave][(uint32_t)(word >> ks) & (R - 1)], 1u);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+        const int dg = q * kBlock + tid;
+        uint32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) c += s_cnt[w][dg];
+        th[(int64_t)dg * pitch + tile] = c;
+    }
 }
 
 // ------------------------------------------------------------- 4. sort
@@ -974,17 +1033,6 @@ __device__ __forceinline__ int frame_of_x(const Frame *frames, int nframes, int6
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (frames[mid].xoff <= cx) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-// Frame holding original point index i: the last frame with off0 <= i.
-__device__ __forceinline__ int frame_of_point(const Frame *frames, int nframes, int64_t i) {
-    int lo = 0, hi = nframes - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (frames[mid].off0 <= i) lo = mid;
         else hi = mid - 1;
     }
     return lo;
@@ -2805,10 +2853,12 @@ static hipError_t launch_sort(uint64_t *keys0, uint64_t *keys1, uint32_t *vals0,
         const uint32_t *srcv = (pass & 1) ? vals1 : vals0;
         uint32_t *dstv = (pass & 1) ? vals0 : vals1;
         hipError_t e;
-        if (timer) timer->begin(kStSortHist, st);
-        k_sort_hist<RB><<<(unsigned)ntiles, kBlock, 0, st>>>(src, P, pass, n, pitch, th);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (timer) timer->end(kStSortHist, st);
+        if (pass > 0) {  // the first pass's digits were counted by the keys kernel
+            if (timer) timer->begin(kStSortHist, st);
+            k_sort_hist<RB><<<(unsigned)ntiles, kBlock, 0, st>>>(src, P, pass, n, pitch, th);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if (timer) timer->end(kStSortHist, st);
+        }
         if (timer) timer->begin(kStSortScan, st);
         k_sort_scan<<<1u << RB, kBlock, 0, st>>>(P, pass, ntiles, pitch, th, dtot);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -2868,15 +2918,6 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
         (int)(nb_pts > tn.stream_blocks ? tn.stream_blocks : (nb_pts < 1 ? 1 : nb_pts));
     const int nb_cells =
         (int)(nb_pts > tn.cell_blocks ? tn.cell_blocks : (nb_pts < 1 ? 1 : nb_pts));
-    // key blocks per frame: one cloud takes the streaming grid; frames take
-    // about one block per 2048 points of an average frame (each block flushes
-    // a full digit histogram, so tiny blocks would cost more in flushes)
-    int keys_pf = nb_stream;
-    if (nframes > 1) {
-        const int64_t per = (n / nframes + 2047) / 2048;
-        keys_pf = (int)(per < nb_stream / nframes ? per : nb_stream / nframes);
-        keys_pf = keys_pf < 1 ? 1 : keys_pf;
-    }
     const int nb_finish = (nframes + kBlock - 1) / kBlock;
     const int nb_list = nb_cells < kListBlocks ? nb_cells : kListBlocks;
     const int radix_bits = tn.radix_bits < kMinRadixBits
@@ -2899,16 +2940,20 @@ hipError_t launch_pipeline(const CallArgs &args, void *ws, const Layout &L, hipS
                                                       args.offsets, args.d_arr, args.min_arr,
                                                       args.max_arr, args.d, args.min_size,
                                                       args.max_size, L.colgrid_cap, radix_bits));
-    FEC_LAUNCH(kStKeys, k_keys<<<(unsigned)(nframes * keys_pf), kBlock, 0, st>>>(
-                            xyz, P, frames, keys_pf, keys0, vals0));
     {
         hipError_t e = hipSuccess;
+        const int64_t pitch = tile_pitch(ntiles);
+#define FEC_KEYS_SORT(RB)                                                                     \
+    FEC_LAUNCH(kStKeys, k_keys<RB><<<(unsigned)ntiles, kBlock, 0, st>>>(                      \
+                            xyz, P, frames, nframes, n, pitch, keys0, vals0, th));            \
+    e = launch_sort<RB>(keys0, keys1, vals0, vals1, P, n, ntiles, th, dtot, st, timer)
         switch (radix_bits) {
-            case 8: e = launch_sort<8>(keys0, keys1, vals0, vals1, P, n, ntiles, th, dtot, st, timer); break;
-            case 9: e = launch_sort<9>(keys0, keys1, vals0, vals1, P, n, ntiles, th, dtot, st, timer); break;
-            case 10: e = launch_sort<10>(keys0, keys1, vals0, vals1, P, n, ntiles, th, dtot, st, timer); break;
-            default: e = launch_sort<11>(keys0, keys1, vals0, vals1, P, n, ntiles, th, dtot, st, timer); break;
+            case 8: FEC_KEYS_SORT(8); break;
+            case 9: FEC_KEYS_SORT(9); break;
+            case 10: FEC_KEYS_SORT(10); break;
+            default: FEC_KEYS_SORT(11); break;
         }
+#undef FEC_KEYS_SORT
         if (e != hipSuccess) return e;
     }
     FEC_LAUNCH(kStGather, k_gather<<<(unsigned)ntiles, kBlock, 0, st>>>(

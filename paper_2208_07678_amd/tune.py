@@ -4,7 +4,8 @@ Five knobs change how the work is laid out on the chip, never the result:
 
 * ``cell_blocks``   -- blocks of the per-cell grid-stride kernels (near and
   far shells, compression, finalize);
-* ``stream_blocks`` -- blocks of the per-point streaming kernels;
+* ``stream_blocks`` -- blocks of the per-point streaming kernel that clears
+  the labels;
 * ``radix_bits``    -- bits per radix-sort pass (8 to 11: fewer passes over
   larger per-tile tables);
 * ``hook_block``    -- threads per block of the hooking kernels (64, 128,
