@@ -750,10 +750,11 @@ __global__ __launch_bounds__(kBlock) void k_sort_scan(const Params *__restrict__
 }
 
 // (3) stable scatter of one tile.
-// Waves per SIMD: as many as the LDS allows blocks per CU (four at 8-bit
-// digits, where 129 registers would allow three: one 8-byte spill at 128;
-// scatter 0.59 -> 0.55 ms per map call).
-constexpr int scatter_waves(int rb) { return rb == 8 ? 4 : (rb <= 10 ? 3 : 2); }
+// Waves per SIMD: as many as the LDS allows blocks per CU (four at 8 and 9
+// bits, three at 10, two at 11).  The per-wave digit counters are 16-bit
+// (they never exceed the tile's 4,096 words), which takes 9-bit digits to
+// 38 KB of LDS per block and four blocks per CU.
+constexpr int scatter_waves(int rb) { return rb <= 9 ? 4 : (rb == 10 ? 3 : 2); }
 
 template <int RB>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(scatter_waves(RB)))) void
@@ -767,7 +768,7 @@ k_sort_scatter(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
     // they go in the tile's LDS buffer; s_base: where the tile's run of each
     // digit goes in the output, then that minus the run's place in the
     // buffer (so buffer slot j goes to s_base[digit] + j)
-    __shared__ uint32_t s_cnt[kBlock / 64][R];
+    __shared__ uint16_t s_cnt[kBlock / 64][R];
     __shared__ uint32_t s_base[R];
     __shared__ uint64_t s_buf[kTile];  // keys in digit order (values after them in pair mode)
     __shared__ uint32_t s_tmp[kBlock / 64];
@@ -808,7 +809,7 @@ k_sort_scatter(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
         const uint32_t below = (uint32_t)__popcll(peers & lanemask_lt());
         const uint32_t prev = s_cnt[wave][dg];
         rk[k] = prev + below;
-        if (valid && below == 0) s_cnt[wave][dg] = prev + (uint32_t)__popcll(peers);
+        if (valid && below == 0) s_cnt[wave][dg] = (uint16_t)(prev + (uint32_t)__popcll(peers));
     }
     __syncthreads();
     {
@@ -823,7 +824,7 @@ k_sort_scatter(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
 #pragma unroll
             for (int w = 0; w < kBlock / 64; ++w) {
                 const uint32_t c = s_cnt[w][dg];
-                s_cnt[w][dg] = run;
+                s_cnt[w][dg] = (uint16_t)run;
                 run += c;
             }
             tv[q] = run;
@@ -834,7 +835,7 @@ k_sort_scatter(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
         for (int q = 0; q < DPT; ++q) {
             const int dg = tid * DPT + q;
 #pragma unroll
-            for (int w = 0; w < kBlock / 64; ++w) s_cnt[w][dg] += tv[q];
+            for (int w = 0; w < kBlock / 64; ++w) s_cnt[w][dg] = (uint16_t)(s_cnt[w][dg] + tv[q]);
             s_base[dg] -= tv[q];  // modulo 2^32; adding the slot restores it
         }
     }
