@@ -239,3 +239,32 @@ def test_labels_into_unaligned_buffer(offset):
         want, _ = oracle.fec(xyz, 0.5, mn, mx)
         assert np.array_equal(got[offset:offset + n], want)
         assert (got[:offset] == 12345).all() and (got[offset + n:] == 12345).all()
+
+
+def test_keys_of_many_radix_passes():
+    # strips 4 km long at d = 2 mm: a 22-bit x field, for 5 to 6 radix
+    # passes at 8 to 10-bit digits (4 at 11) over about 50 tiles; 1 m across
+    # gives 42 key bits (one word per point), 8 m 48 bits (keys and indices
+    # as pairs); 20,000 clumps of 10 points each
+    import paper_2208_07678_amd as fec
+
+    rng = np.random.default_rng(21)
+    ws = fec.new_workspace(200000, "cuda:0")
+    try:
+        for width in (1.0, 8.0):
+            centres = rng.uniform((0, 0, 0), (4000, width, width), size=(20000, 3))
+            x = np.repeat(centres, 10, axis=0) + rng.uniform(-6e-4, 6e-4, size=(200000, 3))
+            x = x.astype(np.float32)[rng.permutation(200000)]
+            want, wk = oracle.fec(x, 2e-3, 1, 200000)
+            for rb in (8, 9, 10, 11):
+                fec.set_tuning(radix_bits=rb)
+                say("case", "strip %g m wide, %d-bit digits" % (width, rb))
+                got, k = gpu_cluster(x, 2e-3, 1, 200000, workspace=ws)
+                st = fec.workspace_stats(ws)
+                tag = "strip %g m, %d bits, stats %s" % (width, rb, st)
+                assert np.array_equal(got, want), "%s: %s" % (tag, describe_mismatch(got, want))
+                assert k == wk, tag
+                assert st["key_bits"] == (42 if width == 1.0 else 48), tag
+                assert st["radix_passes"] == -(-st["key_bits"] // rb), tag
+    finally:
+        fec.set_tuning()
