@@ -474,7 +474,7 @@ __global__ __launch_bounds__(kBlock) void k_plan(const float *__restrict__ parti
     if (kb > 64 && P->status == kStatusOk) P->status = kStatusRange;
     if (nframes == 1 && F0.status != kStatusOk && P->status == kStatusOk) P->status = F0.status;
     P->radix_bits = radix_bits;
-    P->npasses = P->status == kStatusOk ? (kb + radix_bits - 1) / radix_bits : 0;
+    P->npasses = P->status == kStatusOk ? passes_for(radix_bits, kb) : 0;
 }
 
 // Cell key: cx, then cy, then cz.  The cells of one column (cx, cy) are
@@ -651,7 +651,7 @@ __device__ __forceinline__ void block_excl_scan_multi(uint32_t (&v)[DPT], uint32
 template <int RB>
 __global__ __launch_bounds__(kBlock) void k_sort_hist(const uint64_t *__restrict__ src,
                                                       const Params *__restrict__ P, int pass,
-                                                      int64_t n, int64_t pitch,
+                                                      int bit0, int64_t n, int64_t pitch,
                                                       uint32_t *__restrict__ th) {
     constexpr int R = 1 << RB, DPT = R / kBlock;
     if (pass >= P->npasses || P->status != kStatusOk) return;
@@ -662,7 +662,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(const uint64_t *__restrict
     // whole lines (4-byte writes from tiles on different XCDs would each
     // cost a partial line in memory)
     const int64_t tile = xcd_block_eighths();
-    const int shift = P->key_shift + pass * RB;
+    const int shift = P->key_shift + bit0;
     const int64_t base = tile * kTile + (int64_t)wave * (64 * kItems);
     // the tile's words first, their loads overlapping the counters' reset
     uint64_t v[kItems];
@@ -760,7 +760,7 @@ template <int RB>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(scatter_waves(RB)))) void
 k_sort_scatter(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
                const uint32_t *__restrict__ srcv, uint32_t *__restrict__ dstv,
-               const Params *__restrict__ P, int pass, int64_t n, int64_t pitch,
+               const Params *__restrict__ P, int pass, int bit0, int64_t n, int64_t pitch,
                const uint32_t *__restrict__ th, const uint32_t *__restrict__ dtot) {
     constexpr int R = 1 << RB, DPT = R / kBlock;
     if (pass >= P->npasses || P->status != kStatusOk) return;
@@ -778,7 +778,7 @@ k_sort_scatter(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
     // each digit's row of tile positions through one L2
     const int64_t tile = xcd_block_eighths();
     // the tile's words first: their loads overlap the digit bases below
-    const int shift = P->key_shift + pass * RB;
+    const int shift = P->key_shift + bit0;
     const bool pair = P->pair_mode != 0;
     const int64_t base = tile * kTile + (int64_t)wave * (64 * kItems);
     uint64_t v[kItems];
@@ -2840,35 +2840,55 @@ const char *stage_name(int s) {
     return (s >= 0 && s < kNumStages) ? names[s] : "";
 }
 
-// The radix passes at RB bits per digit: passes beyond the device-side count
-// return at once (the pair-mode fallback can need up to a full 64-bit key).
+// One radix pass of W-bit digits over key bits [bit0, bit0 + W): counts (the
+// first pass's come from the keys kernel), per-digit scans, scatter.
+template <int W>
+static hipError_t launch_pass(int pass, int bit0, const uint64_t *src, uint64_t *dst,
+                              const uint32_t *srcv, uint32_t *dstv, const Params *P, int64_t n,
+                              int64_t ntiles, int64_t pitch, uint32_t *th, uint32_t *dtot,
+                              hipStream_t st, Timer *timer) {
+    hipError_t e;
+    if (pass > 0) {
+        if (timer) timer->begin(kStSortHist, st);
+        k_sort_hist<W><<<(unsigned)ntiles, kBlock, 0, st>>>(src, P, pass, bit0, n, pitch, th);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (timer) timer->end(kStSortHist, st);
+    }
+    if (timer) timer->begin(kStSortScan, st);
+    k_sort_scan<<<1u << W, kBlock, 0, st>>>(P, pass, ntiles, pitch, th, dtot);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (timer) timer->end(kStSortScan, st);
+    if (timer) timer->begin(kStSort, st);
+    k_sort_scatter<W><<<(unsigned)ntiles, kBlock, 0, st>>>(src, dst, srcv, dstv, P, pass, bit0, n,
+                                                         pitch, th, dtot);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (timer) timer->end(kStSort, st);
+    return hipSuccess;
+}
+
+// The radix passes of the schedule for RB-bit digits (pass_width /
+// pass_bit0), enough for a 64-bit key (the pair-mode fallback can need one);
+// passes beyond the device-side count return at once.
 template <int RB>
 static hipError_t launch_sort(uint64_t *keys0, uint64_t *keys1, uint32_t *vals0, uint32_t *vals1,
                               const Params *P, int64_t n, int64_t ntiles, uint32_t *th,
                               uint32_t *dtot, hipStream_t st, Timer *timer) {
-    constexpr int kPasses = (64 + RB - 1) / RB;
+    constexpr int kPasses = passes_for(RB, 64);
     const int64_t pitch = tile_pitch(ntiles);
     for (int pass = 0; pass < kPasses; ++pass) {
         const uint64_t *src = (pass & 1) ? keys1 : keys0;
         uint64_t *dst = (pass & 1) ? keys0 : keys1;
         const uint32_t *srcv = (pass & 1) ? vals1 : vals0;
         uint32_t *dstv = (pass & 1) ? vals0 : vals1;
+        const int bit0 = pass_bit0(RB, pass);
         hipError_t e;
-        if (pass > 0) {  // the first pass's digits were counted by the keys kernel
-            if (timer) timer->begin(kStSortHist, st);
-            k_sort_hist<RB><<<(unsigned)ntiles, kBlock, 0, st>>>(src, P, pass, n, pitch, th);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            if (timer) timer->end(kStSortHist, st);
-        }
-        if (timer) timer->begin(kStSortScan, st);
-        k_sort_scan<<<1u << RB, kBlock, 0, st>>>(P, pass, ntiles, pitch, th, dtot);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (timer) timer->end(kStSortScan, st);
-        if (timer) timer->begin(kStSort, st);
-        k_sort_scatter<RB><<<(unsigned)ntiles, kBlock, 0, st>>>(src, dst, srcv, dstv, P, pass, n,
-                                                              pitch, th, dtot);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (timer) timer->end(kStSort, st);
+        if (pass_width(RB, pass) == RB)
+            e = launch_pass<RB>(pass, bit0, src, dst, srcv, dstv, P, n, ntiles, pitch, th, dtot,
+                                st, timer);
+        else  // the 10-bit passes after the first four at 9 bits
+            e = launch_pass<10>(pass, bit0, src, dst, srcv, dstv, P, n, ntiles, pitch, th, dtot,
+                                st, timer);
+        if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }

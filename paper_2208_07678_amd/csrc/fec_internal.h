@@ -22,6 +22,24 @@ constexpr int kMaxRadixBits = 11;
 constexpr int kMaxRadix = 1 << kMaxRadixBits;
 constexpr int kMaxPasses = (64 + kMinRadixBits - 1) / kMinRadixBits;
 constexpr int kDefaultRadixBits = 9;
+// Pass schedule: pass p sorts key bits [pass_bit0(rb, p), + pass_width(rb, p)).
+// At 9-bit digits the passes after the first four (36 bits, the map's 34-bit
+// key and narrower) take 10 bits each, so 7 passes cover a 64-bit key
+// instead of 8; every pass the host enqueues costs a launch even when the
+// device-side pass count makes it return at once.  Other widths are uniform.
+__host__ __device__ constexpr int pass_width(int rb, int p) {
+    return (rb == 9 && p >= 4) ? 10 : rb;
+}
+__host__ __device__ constexpr int pass_bit0(int rb, int p) {
+    return (rb == 9 && p > 4) ? 36 + 10 * (p - 4) : rb * p;
+}
+__host__ __device__ constexpr int passes_for(int rb, int key_bits) {
+    return (rb == 9 && key_bits > 36) ? 4 + (key_bits - 36 + 9) / 10 : (key_bits + rb - 1) / rb;
+}
+static_assert(passes_for(9, 64) == 7 && pass_bit0(9, 6) + pass_width(9, 6) >= 64 &&
+                  pass_bit0(9, 4) == 36 && passes_for(9, 36) == 4 && passes_for(9, 37) == 5,
+              "the 9-bit schedule covers 64 key bits in 7 passes");
+static_assert(passes_for(kMinRadixBits, 64) <= kMaxPasses, "per-pass tables");
 constexpr int kBboxBlocks = 1024;      // max blocks of the bounding-box reduction
 constexpr int kCellBlocks = 4096;      // grid of the grid-stride per-cell kernels
 // Dense column index: one entry per (cx, cy) when the plane has at most

@@ -241,17 +241,27 @@ def test_labels_into_unaligned_buffer(offset):
         assert (got[:offset] == 12345).all() and (got[offset + n:] == 12345).all()
 
 
+def _expected_passes(key_bits, rb):
+    # the library's schedule: at 9-bit digits the passes after the first
+    # four (36 bits) take 10 bits each; other widths are uniform
+    if rb == 9 and key_bits > 36:
+        return 4 + -(-(key_bits - 36) // 10)
+    return -(-key_bits // rb)
+
+
 def test_keys_of_many_radix_passes():
-    # strips 4 km long at d = 2 mm: a 22-bit x field, for 5 to 6 radix
-    # passes at 8 to 10-bit digits (4 at 11) over about 50 tiles; 1 m across
-    # gives 42 key bits (one word per point), 8 m 48 bits (keys and indices
-    # as pairs); 20,000 clumps of 10 points each
+    # strips 4 km long at d = 2 mm: a 22-bit x field, for 4 to 6 radix
+    # passes over about 50 tiles; 1 m across gives 42 key bits, 4 m 46 bits
+    # (5 passes at 9-bit digits where uniform digits would take 6; with the
+    # 18 index bits below it, the last digit reaches the word's top bit),
+    # both one word per point, and 8 m 48 bits (keys and indices as pairs);
+    # 20,000 clumps of 10 points each
     import paper_2208_07678_amd as fec
 
     rng = np.random.default_rng(21)
     ws = fec.new_workspace(200000, "cuda:0")
     try:
-        for width in (1.0, 8.0):
+        for width in (1.0, 4.0, 8.0):
             centres = rng.uniform((0, 0, 0), (4000, width, width), size=(20000, 3))
             x = np.repeat(centres, 10, axis=0) + rng.uniform(-6e-4, 6e-4, size=(200000, 3))
             x = x.astype(np.float32)[rng.permutation(200000)]
@@ -264,7 +274,7 @@ def test_keys_of_many_radix_passes():
                 tag = "strip %g m, %d bits, stats %s" % (width, rb, st)
                 assert np.array_equal(got, want), "%s: %s" % (tag, describe_mismatch(got, want))
                 assert k == wk, tag
-                assert st["key_bits"] == (42 if width == 1.0 else 48), tag
-                assert st["radix_passes"] == -(-st["key_bits"] // rb), tag
+                assert st["key_bits"] == {1.0: 42, 4.0: 46, 8.0: 48}[width], tag
+                assert st["radix_passes"] == _expected_passes(st["key_bits"], rb), tag
     finally:
         fec.set_tuning()
