@@ -293,7 +293,8 @@ int32_t fec_stage_count(void);
  *                  sets every label to -1 before the kept clusters' labels
  *                  (default 4096), in [0, 2^20];
  *   radix_bits     bits per radix-sort pass: 8, 9, 10 or 11 (default 9);
- *                  wider digits take fewer passes over larger tables;
+ *                  wider digits take fewer passes over larger tables (at
+ *                  9, the passes beyond a key's first 36 bits take 10);
  *   hook_block     threads per block of the hooking kernels: 64, 128 or
  *                  256 (default 256);
  *   near_sampling  whether clouds of at least 131,072 cells first link each
