@@ -2583,22 +2583,29 @@ __global__ __launch_bounds__(kBlock) void k_final_cells(const int32_t *__restric
     __shared__ int32_t t_key[kAggSlots];
     __shared__ uint32_t t_sum[kAggSlots], t_min[kAggSlots];
     __shared__ uint32_t s_max;
-    for (int i = threadIdx.x; i < kAggSlots; i += kBlock) {
+    const int64_t M = P->M;
+    const int64_t per = (M + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * per;
+    const int64_t hi = lo + per < M ? lo + per : M;
+    // the table in use: twice the block's cells (at least 64 slots, at most
+    // kAggSlots), so it stays at most half full and small runs of cells
+    // (batches of scans, small clouds) clear and flush few slots
+    int lg = 6;
+    while (lg < 12 && (1ll << lg) < 2 * per) ++lg;
+    const int slots = 1 << lg;
+    static_assert(kAggSlots == 1 << 12, "table sizes up to 2^12");
+    for (int i = threadIdx.x; i < slots; i += kBlock) {
         t_key[i] = -1;
         t_sum[i] = 0;
         t_min[i] = 0xFFFFFFFFu;
     }
     if (threadIdx.x == 0) s_max = 0;
     __syncthreads();
-    const int64_t M = P->M;
-    const int64_t per = (M + gridDim.x - 1) / gridDim.x;
-    const int64_t lo = (int64_t)blockIdx.x * per;
-    const int64_t hi = lo + per < M ? lo + per : M;
     const int lane = __lane_id();
     uint32_t cmax = 0;
 
     auto add = [&](int32_t r, uint32_t c, uint32_t m) {
-        uint32_t h = ((uint32_t)r * 2654435761u) >> (32 - 12);
+        uint32_t h = ((uint32_t)r * 2654435761u) >> (32 - lg);
         for (int probe = 0; probe < 64; ++probe) {
             const int32_t prev = atomicCAS(&t_key[h], -1, r);
             if (prev == -1 || prev == r) {
@@ -2606,7 +2613,7 @@ __global__ __launch_bounds__(kBlock) void k_final_cells(const int32_t *__restric
                 atomicMin(&t_min[h], m);
                 return;
             }
-            h = (h + 1) & (kAggSlots - 1);
+            h = (h + 1) & (uint32_t)(slots - 1);
         }
         atomicAdd(&csize[r], c);  // table crowded: go straight to memory
         atomicMin(&ccanon[r], m);
@@ -2641,7 +2648,7 @@ __global__ __launch_bounds__(kBlock) void k_final_cells(const int32_t *__restric
     cmax = wave_max_u32(cmax);
     if (lane == 0) atomicMax(&s_max, cmax);
     __syncthreads();
-    for (int i = threadIdx.x; i < kAggSlots; i += kBlock) {
+    for (int i = threadIdx.x; i < slots; i += kBlock) {
         const int32_t r = t_key[i];
         if (r >= 0) {
             atomicAdd(&csize[r], t_sum[i]);
