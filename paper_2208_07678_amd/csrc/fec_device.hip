@@ -604,8 +604,10 @@ __global__ __launch_bounds__(kBlock) void k_keys(const float *__restrict__ xyz,
 // ------------------------------------------------------------- 4. sort
 // Stable LSD radix sort of the packed (key, index) words, RB bits per pass
 // (RB from 8 to 11, a launch-time choice: fewer passes against larger
-// per-tile tables), reduce-then-scan: (1) each tile of kTile words counts
-// its digits, (2) one block per digit turns the per-tile counts
+// per-tile tables; at 9, the passes beyond a key's first 36 bits take 10,
+// see pass_width), reduce-then-scan: (1) each tile of kTile words counts
+// its digits (the first pass's are counted by the keys kernel), (2) one
+// block per digit turns the per-tile counts
 // (digit-major) into the position of every tile's run of that digit,
 // counted from the digit's first word, and the digit's total, (3) each tile
 // ranks its words stably, stages them in LDS in digit order and writes each
